@@ -1,0 +1,138 @@
+"""ctypes wrapper of the CPU oracle ``libptalm_ref.so`` (test infrastructure only).
+
+Arrays are numpy float64; a_lm come back as complex128 in healpy order
+(index(l, m) = m*(2*lmax+1-m)//2 + l).  See ``ptalm_ref.h`` for the contract.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libptalm_ref.so")
+_lib = None
+_override = None   # set by use_library(); lets a test run the same calls on another build
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def _bind(path):
+    lib = ctypes.CDLL(path)
+    lib.ptalm_ref_alm_from_points.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, _dp, ctypes.c_int]
+    lib.ptalm_ref_alm_from_points_ld.argtypes = lib.ptalm_ref_alm_from_points.argtypes + [ctypes.c_int]
+    lib.ptalm_ref_alm_entries.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int]
+    lib.ptalm_ref_cl_from_alm.argtypes = [_dp, ctypes.c_int, _dp]
+    lib.ptalm_ref_cross_cl.argtypes = [_dp, _dp, ctypes.c_int, _dp]
+    lib.ptalm_ref_alm_size.argtypes = [ctypes.c_int]
+    lib.ptalm_ref_alm_size.restype = ctypes.c_int64
+    for f in ("ptalm_ref_alm_from_points", "ptalm_ref_alm_from_points_ld", "ptalm_ref_alm_entries",
+              "ptalm_ref_cl_from_alm", "ptalm_ref_cross_cl"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _override is not None:
+        return _override
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build_ref
+        build_ref.build()
+    _lib = _bind(_LIB_PATH)
+    return _lib
+
+
+class use_library:
+    """Context manager: route this module's calls to another build of the oracle
+    (used by the test that plants mistakes in a copy of the source)."""
+
+    def __init__(self, path):
+        self.lib = _bind(path)
+
+    def __enter__(self):
+        global _override
+        self._prev = _override
+        _override = self.lib
+        return self
+
+    def __exit__(self, *exc):
+        global _override
+        _override = self._prev
+        return False
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def alm_size(lmax: int) -> int:
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def alm_from_points(theta, phi, w, lmax: int, nthreads: int = 0, long_double: bool = False,
+                    fp64_trig: bool = False) -> np.ndarray:
+    """a_lm = sum_i w_i conj(Y_lm(theta_i, phi_i)) (eq. alm_def), healpy order, complex128.
+
+    long_double selects the long-double variant; fp64_trig (long-double variant
+    only) rounds cos(theta), sin(theta) to double first, as the FP64 variant does.
+    """
+    lib = _load()
+    theta, phi, w = _f64(theta), _f64(phi), _f64(w)
+    n = theta.size
+    if phi.size != n or w.size != n:
+        raise ValueError("theta, phi, w must have the same length")
+    out = np.zeros(2 * alm_size(lmax), dtype=np.float64)
+    if long_double:
+        rc = lib.ptalm_ref_alm_from_points_ld(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, _ptr(out), nthreads,
+                                              1 if fp64_trig else 0)
+    else:
+        rc = lib.ptalm_ref_alm_from_points(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, _ptr(out), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return out.view(np.complex128)
+
+
+def alm_entries(theta, phi, w, ls, ms, nthreads: int = 0) -> np.ndarray:
+    """Selected a_{l,m} over all points (complex128, one per (ls[k], ms[k]))."""
+    lib = _load()
+    theta, phi, w = _f64(theta), _f64(phi), _f64(w)
+    ls = np.ascontiguousarray(ls, dtype=np.int32)
+    ms = np.ascontiguousarray(ms, dtype=np.int32)
+    out = np.zeros(2 * ls.size, dtype=np.float64)
+    rc = lib.ptalm_ref_alm_entries(_ptr(theta), _ptr(phi), _ptr(w), theta.size, ls.size,
+                                   ls.ctypes.data_as(_ip), ms.ctypes.data_as(_ip), _ptr(out), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return out.view(np.complex128)
+
+
+def cl_from_alm(alm, lmax: int) -> np.ndarray:
+    """C_l = (2l+1)^-1 sum_{m=-l..l} |a_lm|^2 (eq. pseudoCl)."""
+    lib = _load()
+    a = np.ascontiguousarray(alm, dtype=np.complex128).view(np.float64)
+    if a.size != 2 * alm_size(lmax):
+        raise ValueError("alm has the wrong length for lmax")
+    out = np.zeros(lmax + 1)
+    if lib.ptalm_ref_cl_from_alm(_ptr(a), lmax, _ptr(out)) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def cross_cl(alm1, alm2, lmax: int) -> np.ndarray:
+    """C^AB_l = (2l+1)^-1 sum_{m=-l..l} Re(a_lm conj(b_lm))."""
+    lib = _load()
+    a = np.ascontiguousarray(alm1, dtype=np.complex128).view(np.float64)
+    b = np.ascontiguousarray(alm2, dtype=np.complex128).view(np.float64)
+    if a.size != 2 * alm_size(lmax) or b.size != a.size:
+        raise ValueError("alm has the wrong length for lmax")
+    out = np.zeros(lmax + 1)
+    if lib.ptalm_ref_cross_cl(_ptr(a), _ptr(b), lmax, _ptr(out)) != 0:
+        raise ValueError("bad arguments")
+    return out
