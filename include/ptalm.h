@@ -1,0 +1,148 @@
+/*
+ * ptalm.h -- C ABI of the MI355X (gfx950) library for the direct
+ * point-to-harmonic transform of Baleato Lizancos & White, "Harmonic analysis of
+ * discrete tracers of large-scale structure" (arXiv:2312.12285).
+ *
+ * Conventions shared by every entry point
+ *  - a_lm arrays hold 2*T doubles, (re, im) interleaved, in healpy order:
+ *      index(l, m) = m*(2*lmax+1-m)/2 + l,  0 <= m <= l <= lmax,
+ *      T = (lmax+1)(lmax+2)/2.
+ *    Only m >= 0 is stored; a_{l,-m} = (-1)^m conj(a_lm) for real weights
+ *    (Sec. 2.2, the symmetry stated after eq. alm_def).
+ *  - Y_lm is orthonormal on the unit sphere with the Condon-Shortley phase
+ *    (Sec. 2.2 normalisation N_lm; App. A.1 sectoral recurrence sign).
+ *  - Buffers are DEVICE pointers on the current HIP device unless a comment
+ *    says otherwise.  The caller owns every buffer it passes; the library keeps
+ *    no pointer after the work it enqueued has finished.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls are
+ *    asynchronous: outputs are valid once the stream has reached the call's
+ *    work.  Outputs are overwritten, never accumulated into.
+ *  - Errors: arguments are validated synchronously before anything is
+ *    enqueued; on PTALM_EINVAL no output is touched.  PTALM_EDEVICE reports a
+ *    HIP error (a launch failure, or an error left by earlier work that
+ *    surfaced here).  ptalm_last_error() returns a message for the calling
+ *    thread.  No C++ exception crosses this boundary.
+ *  - Thread safety: concurrent calls from different host threads on different
+ *    streams are safe (each call allocates its own scratch, stream-ordered).
+ *  - Results are deterministic: for a given (n, lmax, options, device) every
+ *    reduction is done in a fixed order, so repeated calls are bitwise equal.
+ */
+#ifndef PTALM_H
+#define PTALM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PTALM_OK = 0,
+    PTALM_EINVAL = -1,   /* bad argument; nothing enqueued, outputs untouched   */
+    PTALM_ENOMEM = -2,   /* device allocation of scratch or tables failed        */
+    PTALM_EDEVICE = -3,  /* HIP runtime error                                    */
+    PTALM_EBUSY = -4,    /* server: request does not fit the memory budget now  */
+    PTALM_ENOTSUP = -5   /* option combination not implemented                   */
+} ptalm_status;
+
+/* Largest lmax accepted; keeps T < 2^31 and every index in 32 bits. */
+#define PTALM_LMAX_MAX 16383
+
+/* T = (lmax+1)(lmax+2)/2 for 0 <= lmax <= PTALM_LMAX_MAX, else 0. Host only. */
+int64_t ptalm_alm_size(int lmax);
+
+/* healpy index of (l, m), or -1 unless 0 <= m <= l <= lmax <= PTALM_LMAX_MAX. Host only. */
+int64_t ptalm_alm_index(int lmax, int l, int m);
+
+/*
+ * a_lm = sum_{i<n} w_i Y*_lm(theta_i, phi_i) for 0 <= m <= l <= lmax
+ * (eq. alm_def, Sec. 2.2), in FP64.
+ *   theta, phi, w : n doubles each (structure of arrays).  theta in [0, pi] is
+ *                   a precondition (not checked per element); phi any finite
+ *                   value; weights any finite values, negative allowed.
+ *   alm           : 2*T doubles, output.
+ * n = 0 writes an all-zero a_lm.  Terms whose |Pbar_l^m| stays below about
+ * 2^-1000 (points near the poles at large m) contribute nothing; such terms
+ * cannot change an FP64 result.
+ * PTALM_EINVAL: n < 0, lmax out of range, a NULL pointer with n > 0, alm NULL.
+ */
+int ptalm_alm_from_points(const double *theta, const double *phi, const double *w,
+                          int64_t n, int lmax, double *alm, void *stream);
+
+/* Arithmetic of the transform. */
+typedef enum {
+    PTALM_FP64 = 0,   /* recurrence and sums in FP64                                        */
+    PTALM_MIXED = 1   /* FP32 recurrence and products; FP64 trig, seed exponent, reductions */
+} ptalm_precision;
+
+/* Options of ptalm_alm_from_points_ex.  Zero-initialise, then set fields;
+ * 0 in a tile field means "use the tuned/default value". */
+typedef struct ptalm_opts {
+    int precision;     /* ptalm_precision                                          */
+    int n_weights;     /* >= 1: w holds n_weights rows of n (row-major); alm holds
+                          n_weights blocks of 2*T doubles.  Positions are shared. */
+    int points_per_lane;  /* kernel variant: points held per lane (0 = tuned)     */
+    int l_block;          /* kernel variant: l values per register block (0 = tuned) */
+    int n_slices;      /* point slices = partial results reduced in the second pass (0 = auto) */
+    int m_ranges;      /* contiguous m ranges, one work item per (slice, range) (0 = auto)    */
+} ptalm_opts;
+
+/*
+ * Extended transform: precision and multi-weight batches (several weight
+ * vectors sharing one position set).  With workspace != NULL the call uses
+ * that buffer for its scratch (ws_bytes >= ptalm_workspace_bytes(...)) and
+ * allocates nothing, which allows capture into a HIP graph; with NULL it
+ * allocates stream-ordered scratch itself.
+ * PTALM_EINVAL as above, or opts fields out of range, or ws_bytes too small.
+ * PTALM_ENOTSUP if the (precision, n_weights, tile) combination has no kernel.
+ */
+int ptalm_alm_from_points_ex(const double *theta, const double *phi, const double *w,
+                             int64_t n, int lmax, double *alm, const ptalm_opts *opts,
+                             void *workspace, size_t ws_bytes, void *stream);
+
+/* Scratch bytes ptalm_alm_from_points_ex needs for these arguments (0 on bad
+ * arguments). Host only. */
+size_t ptalm_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts);
+
+/*
+ * Pseudo-spectrum C_l = (2l+1)^-1 sum_{m=-l..l} |a_lm|^2 (eq. pseudoCl), the m<0
+ * half by the symmetry a_{l,-m} = (-1)^m conj(a_lm).
+ *   alm : 2*T doubles (input);  cl : lmax+1 doubles (output).
+ */
+int ptalm_cl_from_alm(const double *alm, int lmax, double *cl, void *stream);
+
+/*
+ * Cross spectrum C^AB_l = (2l+1)^-1 sum_{m=-l..l} Re(a_lm conj(b_lm)), the
+ * generalisation of eq. pseudoCl to two fields (Sec. 1, Sec. 4).
+ *   alm1, alm2 : 2*T doubles each;  cl : lmax+1 doubles.
+ */
+int ptalm_cross_cl(const double *alm1, const double *alm2, int lmax, double *cl, void *stream);
+
+/* y <- y + alpha * x over 2*T doubles (x, y device; alpha host). */
+int ptalm_alm_axpy(double alpha, const double *x, double *y, int lmax, void *stream);
+
+/*
+ * FKP field of Sec. 2.3: alpha = a_00(data) / a_00(randoms), which normalises
+ * the randoms so that alpha*a_00(randoms) = a_00(data), then
+ *   delta  = a(data) - alpha * a(randoms)     (the transform of n_g - alpha n_r, Sec. 1)
+ *   window = alpha * a(randoms)               (w_lm of eq. wldef; C_l of it is W_l)
+ * alpha is written to the device double *alpha_out (may be NULL).  No host
+ * synchronisation.  delta or window may be NULL to skip that output.  Outputs
+ * must not overlap the inputs (PTALM_EINVAL if a pointer is equal to one).
+ * Randoms whose weights sum to zero give a non-finite alpha.
+ */
+int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax,
+                     double *delta, double *window, double *alpha_out, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). Host only. */
+const char *ptalm_last_error(void);
+
+/* Frees the per-device tables cached by earlier calls (coefficients per lmax).
+ * Call only when no work of this library is pending on the current device. */
+int ptalm_release_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTALM_H */

@@ -1,0 +1,302 @@
+// C ABI of the ptalm library: validation, work plans, scratch, launches.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "ptalm.h"
+#include "ptalm_internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const std::string &msg) {
+    g_error = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what) {
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return (e == hipErrorOutOfMemory) ? PTALM_ENOMEM : PTALM_EDEVICE;
+}
+
+bool lmax_ok(int lmax) { return lmax >= 0 && lmax <= PTALM_LMAX_MAX; }
+
+// ---------------------------------------------------------------------------
+// Per-device caches: coefficient tables per lmax, m-range tables per (lmax, R).
+// Entries are built synchronously on a private stream and never modified
+// afterwards, so any stream may read them.
+// ---------------------------------------------------------------------------
+std::mutex g_mu;
+std::map<std::pair<int, int>, ptalm::Tables> g_tables;          // (device, lmax)
+std::map<std::tuple<int, int, int>, int *> g_ranges;            // (device, lmax, R)
+
+int current_device(int *dev) {
+    hipError_t e = hipGetDevice(dev);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "hipGetDevice");
+}
+
+int get_tables(int lmax, const ptalm::Tables **out) {
+    int dev;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_tables.find({dev, lmax});
+    if (it != g_tables.end()) {
+        *out = &it->second;
+        return PTALM_OK;
+    }
+    ptalm::Tables t;
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
+    e = ptalm::build_tables(lmax, &t, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+    if (e != hipSuccess) {
+        hipFree(t.coef);
+        hipFree(t.coef32);
+        hipFree(t.sigma);
+        return fail_hip(e, "building coefficient tables");
+    }
+    auto res = g_tables.emplace(std::make_pair(dev, lmax), t);
+    *out = &res.first->second;
+    return PTALM_OK;
+}
+
+}  // namespace
+
+// Boundaries of R contiguous m ranges of about equal work sum_m (lmax-m+1 + c):
+// range r is [b[r], b[r+1]).  Exposed for the host tests (bit-exact coverage).
+extern "C" int ptalm_plan_m_ranges(int lmax, int R, int *bounds) {
+    if (!lmax_ok(lmax) || R < 1 || R > lmax + 1 || bounds == nullptr) return PTALM_EINVAL;
+    const double setup = 8.0;  // per-order cost of forming weights, in l-steps
+    std::vector<double> cum(lmax + 2, 0.0);
+    for (int m = 0; m <= lmax; ++m) cum[m + 1] = cum[m] + (double)(lmax - m + 1) + setup;
+    const double total = cum[lmax + 1];
+    bounds[0] = 0;
+    int m = 0;
+    for (int r = 1; r < R; ++r) {
+        const double target = total * r / R;
+        while (m < lmax + 1 && cum[m] < target) ++m;
+        // at least one order per range: ranges never empty while R <= lmax+1
+        int lo = bounds[r - 1] + 1, hi = lmax + 1 - (R - r);
+        bounds[r] = std::min(std::max(m, lo), hi);
+        m = bounds[r];
+    }
+    bounds[R] = lmax + 1;
+    return PTALM_OK;
+}
+
+namespace {
+
+int get_ranges(int lmax, int R, const int **out) {
+    int dev;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto key = std::make_tuple(dev, lmax, R);
+    auto it = g_ranges.find(key);
+    if (it != g_ranges.end()) {
+        *out = it->second;
+        return PTALM_OK;
+    }
+    std::vector<int> b(R + 1);
+    ptalm_plan_m_ranges(lmax, R, b.data());
+    int *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(int) * (R + 1));
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc(ranges)");
+    e = hipMemcpy(d, b.data(), sizeof(int) * (R + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(d);
+        return fail_hip(e, "hipMemcpy(ranges)");
+    }
+    g_ranges[key] = d;
+    *out = d;
+    return PTALM_OK;
+}
+
+// Default kernel variant and decomposition.
+constexpr int kDefaultKP = 6;
+constexpr int kDefaultLB = 8;
+constexpr int kTargetItems = 8192;   // (slice, range) items: ~4 per resident wavefront
+constexpr int kMaxSlices = 32;
+
+struct Resolved {
+    int precision, n_weights, kp, lb, S, R;
+    int64_t groups;
+};
+
+int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
+    ptalm_opts d;
+    memset(&d, 0, sizeof d);
+    if (!o) o = &d;
+    r->precision = o->precision;
+    r->n_weights = o->n_weights > 0 ? o->n_weights : 1;
+    if (o->precision != PTALM_FP64 && o->precision != PTALM_MIXED) return fail(PTALM_EINVAL, "bad precision");
+    if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0)
+        return fail(PTALM_EINVAL, "negative option");
+    r->kp = o->points_per_lane ? o->points_per_lane : kDefaultKP;
+    r->lb = o->l_block ? o->l_block : kDefaultLB;
+    const bool have = (r->precision == PTALM_FP64) ? ptalm::fp64_variant_exists(r->kp, r->lb)
+                                                   : ptalm::mixed_variant_exists(r->kp, r->lb);
+    if (!have) return fail(PTALM_ENOTSUP, "no kernel variant with these points_per_lane / l_block");
+    r->groups = (n + 64 * r->kp - 1) / (64 * r->kp);
+    int64_t S = o->n_slices ? o->n_slices : std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, r->groups));
+    if (S > std::max<int64_t>(1, r->groups)) S = std::max<int64_t>(1, r->groups);
+    r->S = (int)S;
+    int R = o->m_ranges ? o->m_ranges : (int)std::max<int64_t>(1, kTargetItems / S);
+    if (R > lmax + 1) R = lmax + 1;
+    r->R = R;
+    return PTALM_OK;
+}
+
+size_t partial_bytes(const Resolved &r, int lmax) {
+    return sizeof(double) * 2 * (size_t)ptalm::tri_size(lmax) * (size_t)r.S;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ptalm_alm_size(int lmax) { return lmax_ok(lmax) ? ptalm::tri_size(lmax) : 0; }
+
+int64_t ptalm_alm_index(int lmax, int l, int m) {
+    if (!lmax_ok(lmax) || m < 0 || l < m || l > lmax) return -1;
+    return ptalm::hp_index(lmax, l, m);
+}
+
+const char *ptalm_last_error(void) { return g_error.c_str(); }
+
+size_t ptalm_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts) {
+    if (n < 0 || !lmax_ok(lmax)) return 0;
+    Resolved r;
+    if (resolve(n, lmax, opts, &r)) return 0;
+    return partial_bytes(r, lmax);
+}
+
+int ptalm_alm_from_points_ex(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
+                             double *alm, const ptalm_opts *opts, void *workspace, size_t ws_bytes,
+                             void *stream_) {
+    g_error.clear();
+    if (n < 0) return fail(PTALM_EINVAL, "n < 0");
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (alm == nullptr) return fail(PTALM_EINVAL, "alm is NULL");
+    if (n > 0 && (theta == nullptr || phi == nullptr || w == nullptr)) return fail(PTALM_EINVAL, "NULL input");
+    Resolved r;
+    int rc = resolve(n, lmax, opts, &r);
+    if (rc) return rc;
+    const size_t need = partial_bytes(r, lmax);
+    if (workspace != nullptr && ws_bytes < need) return fail(PTALM_EINVAL, "workspace too small");
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t T = ptalm::tri_size(lmax);
+    hipError_t e;
+    if (n == 0) {
+        e = hipMemsetAsync(alm, 0, sizeof(double) * 2 * T * r.n_weights, stream);
+        return e == hipSuccess ? PTALM_OK : fail_hip(e, "hipMemsetAsync");
+    }
+    const ptalm::Tables *tab;
+    if ((rc = get_tables(lmax, &tab))) return rc;
+    const int *ranges;
+    if ((rc = get_ranges(lmax, r.R, &ranges))) return rc;
+
+    double *partial = (double *)workspace;
+    bool own = false;
+    if (partial == nullptr) {
+        e = hipMallocAsync((void **)&partial, need, stream);
+        if (e != hipSuccess) return fail_hip(e, "hipMallocAsync(partial)");
+        own = true;
+    }
+    for (int v = 0; v < r.n_weights && rc == PTALM_OK; ++v) {
+        ptalm::AlmArgs a;
+        a.theta = theta;
+        a.phi = phi;
+        a.w = w + (int64_t)v * n;
+        a.n = n;
+        a.lmax = lmax;
+        a.n_ranges = r.R;
+        a.n_slices = r.S;
+        a.groups = r.groups;
+        a.range_m = ranges;
+        a.coef = tab->coef;
+        a.coef32 = tab->coef32;
+        a.partial = partial;
+        a.w_stride = n;
+        a.n_weights = 1;
+        bool supported = true;
+        e = (r.precision == PTALM_FP64) ? ptalm::launch_alm_fp64(a, r.kp, r.lb, stream, &supported)
+                                        : ptalm::launch_alm_mixed(a, r.kp, r.lb, stream, &supported);
+        if (!supported) rc = fail(PTALM_ENOTSUP, "kernel variant not compiled");
+        else if (e != hipSuccess) rc = fail_hip(e, "transform kernel launch");
+        else if ((e = ptalm::launch_reduce_partials(partial, r.S, tab->sigma, lmax, alm + (int64_t)v * 2 * T, stream)) !=
+                 hipSuccess)
+            rc = fail_hip(e, "reduce kernel launch");
+    }
+    if (own) {
+        e = hipFreeAsync(partial, stream);
+        if (e != hipSuccess && rc == PTALM_OK) rc = fail_hip(e, "hipFreeAsync(partial)");
+    }
+    return rc;
+}
+
+int ptalm_alm_from_points(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
+                          double *alm, void *stream) {
+    return ptalm_alm_from_points_ex(theta, phi, w, n, lmax, alm, nullptr, nullptr, 0, stream);
+}
+
+int ptalm_cl_from_alm(const double *alm, int lmax, double *cl, void *stream) {
+    g_error.clear();
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (alm == nullptr || cl == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    hipError_t e = ptalm::launch_cl(alm, nullptr, lmax, cl, (hipStream_t)stream);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "cl kernel launch");
+}
+
+int ptalm_cross_cl(const double *alm1, const double *alm2, int lmax, double *cl, void *stream) {
+    g_error.clear();
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (alm1 == nullptr || alm2 == nullptr || cl == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    hipError_t e = ptalm::launch_cl(alm1, alm2, lmax, cl, (hipStream_t)stream);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "cross_cl kernel launch");
+}
+
+int ptalm_alm_axpy(double alpha, const double *x, double *y, int lmax, void *stream) {
+    g_error.clear();
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (x == nullptr || y == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    hipError_t e = ptalm::launch_axpy(alpha, x, y, 2 * ptalm::tri_size(lmax), (hipStream_t)stream);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "axpy kernel launch");
+}
+
+int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax, double *delta, double *window,
+                     double *alpha_out, void *stream) {
+    g_error.clear();
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (alm_data == nullptr || alm_randoms == nullptr) return fail(PTALM_EINVAL, "NULL input");
+    const void *outs[3] = {delta, window, alpha_out};
+    for (const void *p : outs)
+        if (p != nullptr && (p == alm_data || p == alm_randoms)) return fail(PTALM_EINVAL, "output aliases an input");
+    hipError_t e = ptalm::launch_fkp(alm_data, alm_randoms, lmax, delta, window, alpha_out, (hipStream_t)stream);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "fkp kernel launch");
+}
+
+int ptalm_release_cache(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto &kv : g_tables) {
+        hipFree(kv.second.coef);
+        hipFree(kv.second.coef32);
+        hipFree(kv.second.sigma);
+    }
+    g_tables.clear();
+    for (auto &kv : g_ranges) hipFree(kv.second);
+    g_ranges.clear();
+    return PTALM_OK;
+}
+
+}  // extern "C"

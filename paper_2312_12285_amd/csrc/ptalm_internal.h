@@ -1,0 +1,86 @@
+// Internal declarations of the ptalm HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace ptalm {
+
+// Every per-m segment of the step-coefficient table is padded by this many
+// entries so that an l-block may run past lmax without reading out of bounds.
+constexpr int kCoefPad = 64;
+
+__host__ __device__ inline int64_t tri_size(int lmax) { return (int64_t)(lmax + 1) * (lmax + 2) / 2; }
+
+// healpy index of (l, m)
+__host__ __device__ inline int64_t hp_index(int lmax, int l, int m) {
+    return (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
+}
+
+// start of order m's column in healpy order: index(m, m)
+__host__ __device__ inline int64_t column_start(int lmax, int m) { return hp_index(lmax, m, m); }
+
+// start of order m's padded segment in the step-coefficient table
+__host__ __device__ inline int64_t coef_segment(int lmax, int m) {
+    return column_start(lmax, m) + (int64_t)m * kCoefPad;
+}
+
+__host__ __device__ inline int64_t coef_table_size(int lmax) {
+    return tri_size(lmax) + (int64_t)(lmax + 1) * kCoefPad;
+}
+
+// Device tables for one lmax (built once per device, immutable afterwards).
+struct Tables {
+    int lmax = -1;
+    double *coef = nullptr;   // step coefficients, coef_table_size(lmax)
+    double *sigma = nullptr;  // output scale per (l, m), healpy order, tri_size(lmax)
+    float *coef32 = nullptr;  // FP32 copy of coef for the mixed-precision kernel
+};
+
+// Work decomposition of one transform.
+struct Plan {
+    int points_per_lane = 0;  // KP
+    int l_block = 0;          // LB
+    int n_slices = 0;         // S
+    int n_ranges = 0;         // R
+    int64_t groups = 0;       // ceil(n / (64*KP))
+    std::vector<int> range_m; // R+1 boundaries of the m ranges
+};
+
+// Arguments of the transform kernels (passed by value).
+struct AlmArgs {
+    const double *theta;
+    const double *phi;
+    const double *w;
+    int64_t n;
+    int lmax;
+    int n_ranges;
+    int n_slices;
+    int64_t groups;
+    const int *range_m;       // device, n_ranges+1
+    const double *coef;       // device step coefficients
+    const float *coef32;
+    double *partial;          // device, n_slices * 2T doubles
+    int64_t w_stride;         // multi-weight: distance between weight rows
+    int n_weights;
+};
+
+// --- launchers (defined in the .hip files) ----------------------------------
+hipError_t build_tables(int lmax, Tables *t, hipStream_t stream);
+hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, hipStream_t stream, bool *supported);
+hipError_t launch_alm_mixed(const AlmArgs &a, int kp, int lb, hipStream_t stream, bool *supported);
+hipError_t launch_reduce_partials(const double *partial, int n_slices, const double *sigma, int lmax,
+                                  double *alm, hipStream_t stream);
+hipError_t launch_cl(const double *alm1, const double *alm2, int lmax, double *cl, hipStream_t stream);
+hipError_t launch_axpy(double alpha, const double *x, double *y, int64_t count, hipStream_t stream);
+hipError_t launch_fkp(const double *ad, const double *ar, int lmax, double *delta, double *window,
+                      double *alpha_out, hipStream_t stream);
+
+// Kernel variants compiled into the library, as (points_per_lane, l_block).
+bool fp64_variant_exists(int kp, int lb);
+bool mixed_variant_exists(int kp, int lb);
+
+}  // namespace ptalm

@@ -1,0 +1,184 @@
+"""Python binding of the ptalm C ABI (``include/ptalm.h``): argument marshalling only.
+
+Every function takes torch tensors that live on the GPU, passes their device
+pointers and the current HIP stream to ``libptalm.so``, and returns the output
+tensor.  All arithmetic happens in the library's HIP kernels; there is no CPU
+or PyTorch fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptalm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(or python paper_2312_12285_amd/build.py) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+PTALM_OK, PTALM_EINVAL, PTALM_ENOMEM, PTALM_EDEVICE, PTALM_EBUSY, PTALM_ENOTSUP = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+LMAX_MAX = 16383
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+
+
+class Opts(ctypes.Structure):
+    """Mirror of ``struct ptalm_opts``."""
+    _fields_ = [("precision", ctypes.c_int), ("n_weights", ctypes.c_int), ("points_per_lane", ctypes.c_int),
+                ("l_block", ctypes.c_int), ("n_slices", ctypes.c_int), ("m_ranges", ctypes.c_int)]
+
+
+def _sig(name, restype, argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = argtypes
+    return f
+
+
+_alm_size = _sig("ptalm_alm_size", _i64, [ctypes.c_int])
+_alm_index = _sig("ptalm_alm_index", _i64, [ctypes.c_int, ctypes.c_int, ctypes.c_int])
+_alm = _sig("ptalm_alm_from_points", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, _vp, _vp])
+_alm_ex = _sig("ptalm_alm_from_points_ex", ctypes.c_int,
+               [_vp, _vp, _vp, _i64, ctypes.c_int, _vp, ctypes.POINTER(Opts), _vp, ctypes.c_size_t, _vp])
+_ws_bytes = _sig("ptalm_workspace_bytes", ctypes.c_size_t, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
+_cl = _sig("ptalm_cl_from_alm", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp])
+_cross = _sig("ptalm_cross_cl", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp])
+_axpy = _sig("ptalm_alm_axpy", ctypes.c_int, [ctypes.c_double, _vp, _vp, ctypes.c_int, _vp])
+_fkp = _sig("ptalm_fkp_fields", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp])
+_last_error = _sig("ptalm_last_error", ctypes.c_char_p, [])
+_release = _sig("ptalm_release_cache", ctypes.c_int, [])
+_plan_ranges = _sig("ptalm_plan_m_ranges", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
+
+
+class PtalmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ptalm error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != PTALM_OK:
+        raise PtalmError(rc, _last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return t
+
+
+def alm_size(lmax: int) -> int:
+    return int(_alm_size(lmax))
+
+
+def alm_index(lmax: int, l: int, m: int) -> int:
+    return int(_alm_index(lmax, l, m))
+
+
+def plan_m_ranges(lmax: int, n_ranges: int):
+    b = (ctypes.c_int * (n_ranges + 1))()
+    _check(_plan_ranges(lmax, n_ranges, b))
+    return list(b)
+
+
+def opts(precision=FP64, n_weights=1, points_per_lane=0, l_block=0, n_slices=0, m_ranges=0) -> Opts:
+    return Opts(precision, n_weights, points_per_lane, l_block, n_slices, m_ranges)
+
+
+def alm_from_points(theta, phi, w, lmax: int, out=None, options: Opts | None = None, workspace=None, stream=None):
+    """a_lm = sum_i w_i Y*_lm(theta_i, phi_i); returns float64 [n_weights, 2T] ((re, im) interleaved,
+    healpy order), or [2T] for one weight vector.  w may be [n] or [n_weights, n]."""
+    _dev_f64(theta, "theta"); _dev_f64(phi, "phi"); _dev_f64(w, "w")
+    n = theta.numel()
+    if phi.numel() != n or w.numel() % max(n, 1) != 0:
+        raise ValueError("theta, phi and w rows must have the same length")
+    nw = w.shape[0] if w.dim() == 2 else 1
+    if w.dim() == 2 and w.shape[1] != n:
+        raise ValueError("w must be [n] or [n_weights, n]")
+    T = alm_size(lmax)
+    shape = (nw, 2 * T) if w.dim() == 2 else (2 * T,)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=theta.device)
+    else:
+        _dev_f64(out, "out")
+        if out.numel() != nw * 2 * T:
+            raise ValueError("out has the wrong size")
+    if options is None and nw == 1 and workspace is None:
+        _check(_alm(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, _ptr(out), _stream(stream)))
+    else:
+        o = options if options is not None else opts()
+        o.n_weights = nw
+        ws_ptr, ws_len = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
+        _check(_alm_ex(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, _ptr(out), ctypes.byref(o), ws_ptr, ws_len,
+                       _stream(stream)))
+    return out
+
+
+def workspace_bytes(n: int, lmax: int, options: Opts | None = None) -> int:
+    o = options if options is not None else opts()
+    return int(_ws_bytes(n, lmax, ctypes.byref(o)))
+
+
+def cl_from_alm(alm, lmax: int, out=None, stream=None):
+    """C_l = (2l+1)^-1 sum_{m=-l..l} |a_lm|^2 (float64 [lmax+1])."""
+    _dev_f64(alm, "alm")
+    if out is None:
+        out = torch.empty(lmax + 1, dtype=torch.float64, device=alm.device)
+    _check(_cl(_ptr(alm), lmax, _ptr(out), _stream(stream)))
+    return out
+
+
+def cross_cl(alm1, alm2, lmax: int, out=None, stream=None):
+    """C^AB_l = (2l+1)^-1 sum_{m=-l..l} Re(a_lm conj(b_lm)) (float64 [lmax+1])."""
+    _dev_f64(alm1, "alm1"); _dev_f64(alm2, "alm2")
+    if out is None:
+        out = torch.empty(lmax + 1, dtype=torch.float64, device=alm1.device)
+    _check(_cross(_ptr(alm1), _ptr(alm2), lmax, _ptr(out), _stream(stream)))
+    return out
+
+
+def alm_axpy(alpha: float, x, y, lmax: int, stream=None):
+    """y <- y + alpha x (in place); returns y."""
+    _dev_f64(x, "x"); _dev_f64(y, "y")
+    _check(_axpy(float(alpha), _ptr(x), _ptr(y), lmax, _stream(stream)))
+    return y
+
+
+def fkp_fields(alm_data, alm_randoms, lmax: int, stream=None):
+    """(delta, window, alpha): alpha = a00(d)/a00(r) on the device, delta = a(d) - alpha a(r),
+    window = alpha a(r)."""
+    _dev_f64(alm_data, "alm_data"); _dev_f64(alm_randoms, "alm_randoms")
+    delta = torch.empty_like(alm_data)
+    window = torch.empty_like(alm_data)
+    alpha = torch.empty(1, dtype=torch.float64, device=alm_data.device)
+    _check(_fkp(_ptr(alm_data), _ptr(alm_randoms), lmax, _ptr(delta), _ptr(window), _ptr(alpha), _stream(stream)))
+    return delta, window, alpha
+
+
+def release_cache():
+    _check(_release())
+
+
+def last_error() -> str:
+    return _last_error().decode()
+
+
+def as_complex(alm):
+    """View a float64 (re, im)-interleaved a_lm tensor as complex128."""
+    return torch.view_as_complex(alm.view(*alm.shape[:-1], -1, 2))

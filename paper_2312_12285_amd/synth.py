@@ -45,14 +45,21 @@ def in_mask(theta, phi, dec_min_deg: float = -10.0, b_min_deg: float = 20.0):
     return (dec > math.radians(dec_min_deg)) & (np.abs(sinb) > math.sin(math.radians(b_min_deg)))
 
 
-def uniform_in_mask(n: int, seed: int, chunk: int = 10_000_000):
-    """n positions uniform on the sphere restricted to the survey mask."""
+MASK_CHUNK = 1 << 20
+
+
+def uniform_in_mask(n: int, seed: int):
+    """n positions uniform on the sphere restricted to the survey mask.
+
+    Candidates are drawn in fixed chunks of 2^20, so the first k points of a
+    catalog do not depend on its size: uniform_in_mask(k, s) equals
+    uniform_in_mask(N, s)[:k] for k <= N (subsamples are prefixes)."""
     rng = np.random.default_rng(seed)
     theta = np.empty(n)
     phi = np.empty(n)
     filled = 0
     while filled < n:
-        m = min(chunk, max(1024, int((n - filled) / 0.38) + 1024))
+        m = MASK_CHUNK
         u = rng.uniform(-1.0, 1.0, m)
         p = rng.uniform(0.0, TWO_PI, m)
         t = np.arccos(u)

@@ -1,0 +1,89 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/ptalm.h declares, and its integer planning is exact."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2312_12285_amd", "libptalm.so")
+HEADER = os.path.join(ROOT, "include", "ptalm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libptalm.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|size_t|const char \*)\s*\**\s*(ptalm_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("ptalm_alm_from_points", "ptalm_cl_from_alm", "ptalm_cross_cl", "ptalm_alm_from_points_ex",
+                 "ptalm_fkp_fields", "ptalm_alm_axpy", "ptalm_last_error", "ptalm_alm_size", "ptalm_alm_index"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in ptalm.h but not exported"
+
+
+def test_alm_size_and_index_bit_exact(lib):
+    lib.ptalm_alm_size.restype = ctypes.c_int64
+    lib.ptalm_alm_index.restype = ctypes.c_int64
+    for lmax in (0, 1, 2, 7, 64, 1024, 3072, 16383):
+        assert lib.ptalm_alm_size(lmax) == (lmax + 1) * (lmax + 2) // 2
+    assert lib.ptalm_alm_size(-1) == 0 and lib.ptalm_alm_size(16384) == 0
+    for lmax in (0, 1, 5, 33):
+        seen = []
+        for m in range(lmax + 1):
+            for l in range(m, lmax + 1):
+                seen.append(lib.ptalm_alm_index(lmax, l, m))
+        assert seen == list(range((lmax + 1) * (lmax + 2) // 2))   # healpy order, dense, m-major
+    assert lib.ptalm_alm_index(10, 3, 4) == -1 and lib.ptalm_alm_index(10, 11, 0) == -1
+    assert lib.ptalm_alm_index(10, 3, -1) == -1
+
+
+@pytest.mark.parametrize("lmax,R", [(0, 1), (10, 4), (64, 65), (1024, 256), (3072, 256), (3072, 3073), (5, 1)])
+def test_m_ranges_partition_every_order_once(lib, lmax, R):
+    b = (ctypes.c_int * (R + 1))()
+    assert lib.ptalm_plan_m_ranges(lmax, R, b) == 0
+    b = list(b)
+    assert b[0] == 0 and b[-1] == lmax + 1
+    assert all(b[i] < b[i + 1] for i in range(R))          # non-empty, increasing
+    # balanced: no range exceeds the mean work by more than one order's work
+    work = np.array([lmax - m + 1 + 8 for m in range(lmax + 1)], dtype=float)
+    per = [work[b[i]:b[i + 1]].sum() for i in range(R)]
+    assert max(per) <= work.sum() / R + work.max() + 1e-9
+
+
+def test_m_ranges_rejects_bad_arguments(lib):
+    b = (ctypes.c_int * 8)()
+    assert lib.ptalm_plan_m_ranges(5, 7, b) == -1      # more ranges than orders
+    assert lib.ptalm_plan_m_ranges(-1, 1, b) == -1
+    assert lib.ptalm_plan_m_ranges(5, 0, b) == -1
+
+
+def test_workspace_bytes_matches_plan(lib):
+    class Opts(ctypes.Structure):
+        _fields_ = [(f, ctypes.c_int) for f in ("precision", "n_weights", "points_per_lane", "l_block",
+                                                  "n_slices", "m_ranges")]
+    lib.ptalm_workspace_bytes.restype = ctypes.c_size_t
+    lib.ptalm_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Opts)]
+    o = Opts(0, 1, 6, 8, 16, 0)
+    T = 3073 * 3074 // 2
+    assert lib.ptalm_workspace_bytes(10 ** 8, 3072, ctypes.byref(o)) == 16 * 2 * T * 8
+    o = Opts(0, 1, 6, 8, 0, 0)    # auto slices, clamped to the number of point groups (1 here)
+    assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 1 * 2 * (65 * 66 // 2) * 8
+    o = Opts(0, 1, 7, 8, 0, 0)    # no such kernel variant
+    assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0
+    o = Opts(5, 1, 0, 0, 0, 0)    # bad precision
+    assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0
