@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the direct point-to-harmonic transform on one MI355X.
+
+A step is one pass of the whole path over one synthetic catalog resident in
+HBM: the transform a_lm = sum_i w_i Y*_lm (ptalm_alm_from_points) followed by
+its pseudo-spectrum (ptalm_cl_from_alm); the two-catalog workload adds the FKP
+field (alpha, delta = a_d - alpha a_r, window = alpha a_r) and both spectra.
+The metric is point.(l,m) terms per second: terms = n * (lmax+1)(lmax+2)/2 per
+transform.  Prints ONE JSON line.
+
+Workloads (--workload):
+  randoms3072  1e8 uniform-in-mask randoms, unit weights, lmax 3072   (default)
+  galaxies1024 2e6 clustered galaxies (lognormal weights) + 2e7 randoms, lmax 1024
+  fullsky64    1e4 uniform full-sky points, unit weights, lmax 64
+
+Besides value, the line carries the roofline of the transform kernel (its
+algorithmic FP64 work, 7 flops per term, over its device time measured with
+HIP events the library records on the launch stream), the CPU oracle timed on
+a bounded prefix of the same catalog, and a sampled parity check of the full
+result against oracle entries computed over every point.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 flop/clk/CU)
+FLOPS_PER_TERM = 7            # recurrence multiply + FMA, two accumulate FMAs
+METRIC = "point\u00b7(l,m) terms/s FP64 vs mixed at stated rel err; served p50/p99 latency"
+UNIT = "point\u00b7(l,m) terms/s"
+
+WORKLOADS = {
+    "randoms3072": dict(desc="masked randoms n=1e8, unit weights, lmax=3072", lmax=3072),
+    "galaxies1024": dict(desc="masked galaxies n=2e6 (2% jittered copies, lognormal sigma=0.3) + masked randoms "
+                              "n=2e7, lmax=1024, C_l of galaxies - alpha randoms and W_l", lmax=1024),
+    "fullsky64": dict(desc="full-sky uniform n=1e4, unit weights, lmax=64", lmax=64),
+}
+
+
+def tri(lmax):
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def make_catalogs(name, scale):
+    from paper_2312_12285_amd import synth
+    if name == "randoms3072":
+        return [("randoms", synth.masked_randoms(int(1e8 * scale), seed=31))]
+    if name == "galaxies1024":
+        return [("galaxies", synth.masked_galaxies(int(2e6 * scale), seed_pos=21, seed_w=22)),
+                ("randoms", synth.masked_randoms(int(2e7 * scale), seed=23))]
+    if name == "fullsky64":
+        return [("points", synth.fullsky_uniform(10_000, seed=1))]
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(cats, lmax, seconds_target):
+    """The oracle, untuned, on a prefix of the first catalog sized for ~seconds_target."""
+    from oracle import ref
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    cat = cats[0][1]
+    T = tri(lmax)
+    k = max(64, min(cat.n, 512))
+    t0 = time.time()
+    ref.alm_from_points(cat.theta[:k], cat.phi[:k], cat.w[:k], lmax, nthreads=nthreads)
+    dt = time.time() - t0
+    rate = k * T / dt
+    k2 = int(min(cat.n, max(k, rate * seconds_target / T)))
+    if k2 > k:
+        t0 = time.time()
+        ref.alm_from_points(cat.theta[:k2], cat.phi[:k2], cat.w[:k2], lmax, nthreads=nthreads)
+        dt = time.time() - t0
+        k = k2
+        rate = k * T / dt
+    return {"value": rate, "unit": UNIT, "cores": nthreads, "kind": "oracle",
+            "sample": f"first {k} points of the {cats[0][0]} catalog at lmax {lmax} ({k * T:.3g} terms, {dt:.1f} s)"}
+
+
+def sampled_parity(cat, lmax, alm_dev):
+    """Compare a few a_lm of the full result with oracle entries summed over every point."""
+    import numpy as np
+    from oracle import ref
+    from paper_2312_12285_amd import ptalm
+    pairs = [(0, 0), (1, 0), (1, 1), (lmax, lmax), (lmax, lmax - 1), (lmax, lmax - 3),
+             (lmax // 2, lmax // 2 - 2), (min(40, lmax), min(17, lmax))]
+    ls = np.array([p[0] for p in pairs]); ms = np.array([p[1] for p in pairs])
+    t0 = time.time()
+    want = ref.alm_entries(cat.theta, cat.phi, cat.w, ls, ms)
+    dt = time.time() - t0
+    a = ptalm.as_complex(alm_dev).cpu().numpy()
+    got = np.array([a[ptalm.alm_index(lmax, l, m)] for l, m in pairs])
+    # each entry against the size of a typical coefficient at its l
+    cl = ptalm.cl_from_alm(alm_dev, lmax).cpu().numpy()
+    scale = np.sqrt(np.maximum(cl[ls], 1e-300))
+    rel = np.abs(got - want) / scale
+    return {"entries": [f"({l},{m})" for l, m in pairs], "max_err_over_rms_l": float(rel.max()),
+            "oracle_seconds": round(dt, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="randoms3072", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--points-per-lane", type=int, default=0)
+    ap.add_argument("--l-block", type=int, default=0)
+    ap.add_argument("--scale", type=float, default=1.0, help="catalog size factor (1 = the named workload)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
+              "in DESIGN.md, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2312_12285_amd import ptalm
+
+    wl = WORKLOADS[args.workload]
+    lmax = wl["lmax"]
+    T = tri(lmax)
+    print(f"[bench] generating {args.workload} (scale {args.scale})", file=sys.stderr, flush=True)
+    t0 = time.time()
+    cats = make_catalogs(args.workload, args.scale)
+    print(f"[bench] generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    dev = []
+    for name, c in cats:
+        dev.append((name, torch.as_tensor(c.theta).cuda(), torch.as_tensor(c.phi).cuda(),
+                    torch.as_tensor(c.w).cuda(), c.n))
+    prec = ptalm.MIXED if args.precision == "mixed" else ptalm.FP64
+    opt = ptalm.opts(precision=prec, points_per_lane=args.points_per_lane, l_block=args.l_block, timing=1)
+    outs = [torch.empty(2 * T, dtype=torch.float64, device="cuda") for _ in dev]
+    cls = [torch.empty(lmax + 1, dtype=torch.float64, device="cuda") for _ in range(2)]
+    kernel_ms = []
+
+    def step():
+        ms = 0.0
+        for (name, t, p, w, n), out in zip(dev, outs):
+            ptalm.alm_from_points(t, p, w, lmax, out=out, options=opt)
+            ms += ptalm.last_timing_ms()
+        if len(dev) == 2:
+            delta, window, alpha = ptalm.fkp_fields(outs[0], outs[1], lmax)
+            ptalm.cl_from_alm(delta, lmax, out=cls[0])
+            ptalm.cl_from_alm(window, lmax, out=cls[1])
+        else:
+            ptalm.cl_from_alm(outs[0], lmax, out=cls[0])
+        kernel_ms.append(ms)
+
+    # build the per-lmax tables outside the timed region
+    ptalm.alm_from_points(dev[0][1][:1], dev[0][2][:1], dev[0][3][:1], lmax)
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
+        step()
+    torch.cuda.synchronize()
+    kernel_ms.clear()
+    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    terms_per_step = sum(n for *_, n in dev) * T
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = terms_per_step * args.steps / elapsed
+    k_ms = float(np.mean(kernel_ms)) / len(dev)           # average transform-kernel launch
+    flops_per_launch = FLOPS_PER_TERM * terms_per_step / len(dev)
+    achieved = flops_per_launch / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "alm_fp64_kernel" if prec == ptalm.FP64 else "alm_mixed_kernel",
+                "kernel_ms_per_launch": round(k_ms, 3), "flops_per_term": FLOPS_PER_TERM}
+
+    line = {"metric": METRIC, "value": value, "unit": UNIT,
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if prec == ptalm.FP64 else "f32+f64", "data": "synthetic",
+            "config": {"workload": wl["desc"], "lmax": lmax, "points": sum(n for *_, n in dev),
+                       "terms_per_step": terms_per_step, "precision": args.precision,
+                       "points_per_lane": args.points_per_lane or "default", "l_block": args.l_block or "default"},
+            "roofline": roofline}
+    if not args.no_check:
+        print("[bench] sampled parity against oracle entries", file=sys.stderr, flush=True)
+        line["parity"] = sampled_parity(cats[-1][1], lmax, outs[-1])
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(cats, lmax, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,6 +86,10 @@ typedef struct ptalm_opts {
     int l_block;          /* kernel variant: l values per register block (0 = tuned) */
     int n_slices;      /* point slices = partial results reduced in the second pass (0 = auto) */
     int m_ranges;      /* contiguous m ranges, one work item per (slice, range) (0 = auto)    */
+    int reduction;     /* cross-lane reduction variant: 0 = tuned default, else
+                          1 + (register butterfly stage ? 1 : 0) + (pipelined ? 2 : 0)     */
+    int timing;        /* != 0: record HIP events around the transform kernel(s) on `stream`;
+                          read them with ptalm_last_timing()                               */
 } ptalm_opts;
 
 /*
@@ -134,6 +138,13 @@ int ptalm_alm_axpy(double alpha, const double *x, double *y, int lmax, void *str
  */
 int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax,
                      double *delta, double *window, double *alpha_out, void *stream);
+
+/* Device time of the transform kernel(s) of the last ptalm_alm_from_points_ex
+ * call made on this thread with opts->timing set: from just before the first
+ * transform kernel to just after the last one, on that call's stream.  Blocks
+ * until that work has finished.  PTALM_EINVAL if no timed call was made.
+ * Host only. */
+int ptalm_last_timing(double *transform_ms);
 
 /* Message of the last failed call on this thread ("" if none). Host only. */
 const char *ptalm_last_error(void);

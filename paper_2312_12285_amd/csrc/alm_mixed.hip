@@ -3,9 +3,9 @@
 
 namespace ptalm {
 
-bool mixed_variant_exists(int, int) { return false; }
+bool mixed_variant_exists(int, int, int) { return false; }
 
-hipError_t launch_alm_mixed(const AlmArgs &, int, int, hipStream_t, bool *supported) {
+hipError_t launch_alm_mixed(const AlmArgs &, int, int, int, hipStream_t, bool *supported) {
     *supported = false;
     return hipSuccess;
 }

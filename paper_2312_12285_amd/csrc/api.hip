@@ -16,6 +16,13 @@ namespace {
 
 thread_local std::string g_error;
 
+// Events of the last timed transform on this thread (created on first use).
+struct TimingEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool valid = false;
+};
+thread_local TimingEvents g_timing;
+
 int fail(int code, const std::string &msg) {
     g_error = msg;
     return code;
@@ -124,12 +131,13 @@ int get_ranges(int lmax, int R, const int **out) {
 
 // Default kernel variant and decomposition.
 constexpr int kDefaultKP = 6;
-constexpr int kDefaultLB = 8;
+constexpr int kDefaultLB = 16;
+constexpr int kDefaultMode = 3;  // register butterfly stage + pipelined reduction
 constexpr int kTargetItems = 8192;   // (slice, range) items: ~4 per resident wavefront
 constexpr int kMaxSlices = 32;
 
 struct Resolved {
-    int precision, n_weights, kp, lb, S, R;
+    int precision, n_weights, kp, lb, mode, S, R;
     int64_t groups;
 };
 
@@ -140,13 +148,16 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     r->precision = o->precision;
     r->n_weights = o->n_weights > 0 ? o->n_weights : 1;
     if (o->precision != PTALM_FP64 && o->precision != PTALM_MIXED) return fail(PTALM_EINVAL, "bad precision");
-    if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0)
-        return fail(PTALM_EINVAL, "negative option");
+    if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0 ||
+        o->reduction < 0 || o->reduction > 4)
+        return fail(PTALM_EINVAL, "option out of range");
+    if (o->n_slices > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
     r->kp = o->points_per_lane ? o->points_per_lane : kDefaultKP;
     r->lb = o->l_block ? o->l_block : kDefaultLB;
-    const bool have = (r->precision == PTALM_FP64) ? ptalm::fp64_variant_exists(r->kp, r->lb)
-                                                   : ptalm::mixed_variant_exists(r->kp, r->lb);
-    if (!have) return fail(PTALM_ENOTSUP, "no kernel variant with these points_per_lane / l_block");
+    r->mode = o->reduction ? o->reduction - 1 : kDefaultMode;
+    const bool have = (r->precision == PTALM_FP64) ? ptalm::fp64_variant_exists(r->kp, r->lb, r->mode)
+                                                   : ptalm::mixed_variant_exists(r->kp, r->lb, r->mode);
+    if (!have) return fail(PTALM_ENOTSUP, "no kernel variant with these points_per_lane / l_block / reduction");
     r->groups = (n + 64 * r->kp - 1) / (64 * r->kp);
     int64_t S = o->n_slices ? o->n_slices : std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, r->groups));
     if (S > std::max<int64_t>(1, r->groups)) S = std::max<int64_t>(1, r->groups);
@@ -173,6 +184,17 @@ int64_t ptalm_alm_index(int lmax, int l, int m) {
 }
 
 const char *ptalm_last_error(void) { return g_error.c_str(); }
+
+int ptalm_last_timing(double *transform_ms) {
+    if (transform_ms == nullptr || !g_timing.valid) return fail(PTALM_EINVAL, "no timed call on this thread");
+    hipError_t e = hipEventSynchronize(g_timing.stop);
+    if (e != hipSuccess) return fail_hip(e, "hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, g_timing.start, g_timing.stop);
+    if (e != hipSuccess) return fail_hip(e, "hipEventElapsedTime");
+    *transform_ms = ms;
+    return PTALM_OK;
+}
 
 size_t ptalm_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts) {
     if (n < 0 || !lmax_ok(lmax)) return 0;
@@ -213,6 +235,12 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
         if (e != hipSuccess) return fail_hip(e, "hipMallocAsync(partial)");
         own = true;
     }
+    const bool timed = opts != nullptr && opts->timing != 0;
+    if (timed) {
+        g_timing.valid = false;
+        if (!g_timing.start && (e = hipEventCreate(&g_timing.start)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+        if (!g_timing.stop && (e = hipEventCreate(&g_timing.stop)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+    }
     for (int v = 0; v < r.n_weights && rc == PTALM_OK; ++v) {
         ptalm::AlmArgs a;
         a.theta = theta;
@@ -230,8 +258,17 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
         a.w_stride = n;
         a.n_weights = 1;
         bool supported = true;
-        e = (r.precision == PTALM_FP64) ? ptalm::launch_alm_fp64(a, r.kp, r.lb, stream, &supported)
-                                        : ptalm::launch_alm_mixed(a, r.kp, r.lb, stream, &supported);
+        if (timed && v == 0 && (e = hipEventRecord(g_timing.start, stream)) != hipSuccess) {
+            rc = fail_hip(e, "hipEventRecord");
+            break;
+        }
+        e = (r.precision == PTALM_FP64) ? ptalm::launch_alm_fp64(a, r.kp, r.lb, r.mode, stream, &supported)
+                                        : ptalm::launch_alm_mixed(a, r.kp, r.lb, r.mode, stream, &supported);
+        if (timed && v == r.n_weights - 1 && e == hipSuccess && supported) {
+            hipError_t e2 = hipEventRecord(g_timing.stop, stream);
+            if (e2 != hipSuccess) e = e2;
+            else g_timing.valid = true;
+        }
         if (!supported) rc = fail(PTALM_ENOTSUP, "kernel variant not compiled");
         else if (e != hipSuccess) rc = fail_hip(e, "transform kernel launch");
         else if ((e = ptalm::launch_reduce_partials(partial, r.S, tab->sigma, lmax, alm + (int64_t)v * 2 * T, stream)) !=

@@ -70,8 +70,8 @@ struct AlmArgs {
 
 // --- launchers (defined in the .hip files) ----------------------------------
 hipError_t build_tables(int lmax, Tables *t, hipStream_t stream);
-hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, hipStream_t stream, bool *supported);
-hipError_t launch_alm_mixed(const AlmArgs &a, int kp, int lb, hipStream_t stream, bool *supported);
+hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
+hipError_t launch_alm_mixed(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
 hipError_t launch_reduce_partials(const double *partial, int n_slices, const double *sigma, int lmax,
                                   double *alm, hipStream_t stream);
 hipError_t launch_cl(const double *alm1, const double *alm2, int lmax, double *cl, hipStream_t stream);
@@ -79,8 +79,9 @@ hipError_t launch_axpy(double alpha, const double *x, double *y, int64_t count, 
 hipError_t launch_fkp(const double *ad, const double *ar, int lmax, double *delta, double *window,
                       double *alpha_out, hipStream_t stream);
 
-// Kernel variants compiled into the library, as (points_per_lane, l_block).
-bool fp64_variant_exists(int kp, int lb);
-bool mixed_variant_exists(int kp, int lb);
+// Kernel variants compiled into the library, as (points_per_lane, l_block, mode)
+// with mode = register butterfly stage (bit 0) | pipelined reduction (bit 1).
+bool fp64_variant_exists(int kp, int lb, int mode);
+bool mixed_variant_exists(int kp, int lb, int mode);
 
 }  // namespace ptalm

@@ -32,7 +32,8 @@ _i64 = ctypes.c_int64
 class Opts(ctypes.Structure):
     """Mirror of ``struct ptalm_opts``."""
     _fields_ = [("precision", ctypes.c_int), ("n_weights", ctypes.c_int), ("points_per_lane", ctypes.c_int),
-                ("l_block", ctypes.c_int), ("n_slices", ctypes.c_int), ("m_ranges", ctypes.c_int)]
+                ("l_block", ctypes.c_int), ("n_slices", ctypes.c_int), ("m_ranges", ctypes.c_int),
+                ("reduction", ctypes.c_int), ("timing", ctypes.c_int)]
 
 
 def _sig(name, restype, argtypes):
@@ -53,6 +54,7 @@ _cross = _sig("ptalm_cross_cl", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]
 _axpy = _sig("ptalm_alm_axpy", ctypes.c_int, [ctypes.c_double, _vp, _vp, ctypes.c_int, _vp])
 _fkp = _sig("ptalm_fkp_fields", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp])
 _last_error = _sig("ptalm_last_error", ctypes.c_char_p, [])
+_last_timing = _sig("ptalm_last_timing", ctypes.c_int, [ctypes.POINTER(ctypes.c_double)])
 _release = _sig("ptalm_release_cache", ctypes.c_int, [])
 _plan_ranges = _sig("ptalm_plan_m_ranges", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
 
@@ -97,8 +99,18 @@ def plan_m_ranges(lmax: int, n_ranges: int):
     return list(b)
 
 
-def opts(precision=FP64, n_weights=1, points_per_lane=0, l_block=0, n_slices=0, m_ranges=0) -> Opts:
-    return Opts(precision, n_weights, points_per_lane, l_block, n_slices, m_ranges)
+def opts(precision=FP64, n_weights=1, points_per_lane=0, l_block=0, n_slices=0, m_ranges=0, reduction=0,
+         timing=0) -> Opts:
+    """reduction: 0 = tuned default, else 1 + register-stage (1) + pipelined (2)."""
+    return Opts(precision, n_weights, points_per_lane, l_block, n_slices, m_ranges, reduction, timing)
+
+
+def last_timing_ms() -> float:
+    """Device milliseconds of the transform kernel(s) of the last call made with timing=1
+    on this thread (HIP events recorded by the library on the call's stream)."""
+    v = ctypes.c_double()
+    _check(_last_timing(ctypes.byref(v)))
+    return v.value
 
 
 def alm_from_points(theta, phi, w, lmax: int, out=None, options: Opts | None = None, workspace=None, stream=None):

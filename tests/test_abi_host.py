@@ -75,15 +75,15 @@ def test_m_ranges_rejects_bad_arguments(lib):
 def test_workspace_bytes_matches_plan(lib):
     class Opts(ctypes.Structure):
         _fields_ = [(f, ctypes.c_int) for f in ("precision", "n_weights", "points_per_lane", "l_block",
-                                                  "n_slices", "m_ranges")]
+                                                  "n_slices", "m_ranges", "reduction", "timing")]
     lib.ptalm_workspace_bytes.restype = ctypes.c_size_t
     lib.ptalm_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Opts)]
-    o = Opts(0, 1, 6, 8, 16, 0)
+    o = Opts(0, 1, 6, 16, 16, 0, 0, 0)
     T = 3073 * 3074 // 2
     assert lib.ptalm_workspace_bytes(10 ** 8, 3072, ctypes.byref(o)) == 16 * 2 * T * 8
-    o = Opts(0, 1, 6, 8, 0, 0)    # auto slices, clamped to the number of point groups (1 here)
+    o = Opts(0, 1, 6, 16, 0, 0, 0, 0)    # auto slices, clamped to the number of point groups (1 here)
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 1 * 2 * (65 * 66 // 2) * 8
-    o = Opts(0, 1, 7, 8, 0, 0)    # no such kernel variant
+    o = Opts(0, 1, 7, 16, 0, 0, 0, 0)    # no such kernel variant
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0
-    o = Opts(5, 1, 0, 0, 0, 0)    # bad precision
+    o = Opts(5, 1, 0, 0, 0, 0, 0, 0)    # bad precision
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0

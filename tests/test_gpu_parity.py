@@ -73,16 +73,22 @@ def test_fullsky_lmax64_n1e4(lib, oracle):
     assert_gate(a, ref, 64, what="fullsky 1e4")
 
 
-@pytest.mark.parametrize("kp,lb", [(4, 8), (6, 8), (8, 8), (10, 8), (12, 8), (8, 16), (8, 32), (16, 8)])
-def test_every_kernel_variant(lib, oracle, kp, lb):
+FP64_VARIANTS = [(6, 8, 0, 0), (7, 8, 0, 0), (6, 16, 0, 0), (6, 16, 1, 0), (6, 16, 1, 1), (6, 16, 0, 1),
+                 (5, 16, 1, 1), (8, 16, 1, 1), (10, 16, 1, 1), (12, 16, 1, 1), (12, 16, 0, 1), (14, 8, 0, 1),
+                 (14, 8, 1, 1), (12, 8, 1, 1), (4, 8, 0, 0), (8, 32, 0, 0), (16, 8, 0, 0)]
+
+
+@pytest.mark.parametrize("kp,lb,swap,pipe", FP64_VARIANTS)
+def test_every_kernel_variant(lib, oracle, kp, lb, swap, pipe):
     """Ragged point count (not a multiple of 64*KP) and odd lmax (partial l-blocks)."""
     from paper_2312_12285_amd.synth import masked_galaxies
-    say(f"case: variant kp={kp} lb={lb} n=5003 lmax=257")
+    say(f"case: variant kp={kp} lb={lb} swap={swap} pipe={pipe} n=5003 lmax=257")
     cat = masked_galaxies(5003, seed_pos=5, seed_w=6)
     lmax = 257
     ref = oracle.alm_from_points(cat.theta, cat.phi, cat.w, lmax)
-    a = gpu_alm(lib, cat.theta, cat.phi, cat.w, lmax, points_per_lane=kp, l_block=lb)
-    assert_gate(a, ref, lmax, what=f"kp={kp} lb={lb}")
+    a = gpu_alm(lib, cat.theta, cat.phi, cat.w, lmax, points_per_lane=kp, l_block=lb,
+                reduction=1 + swap + 2 * pipe)
+    assert_gate(a, ref, lmax, what=f"kp={kp} lb={lb} swap={swap} pipe={pipe}")
 
 
 @pytest.mark.parametrize("S,R", [(1, 1), (1, 258), (3, 7), (7, 100), (2, 0), (0, 1)])
