@@ -42,6 +42,31 @@ WORKLOADS = {
 }
 
 
+PROFILES = os.path.join(HERE, "profiles")
+KERNEL_SOURCE = os.path.join(HERE, "paper_2312_12285_amd", "csrc", "alm_direct.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic(workload, variant):
+    """HBM bytes per launch of the transform kernel from the committed rocprofv3
+    PMC summary (FETCH_SIZE, WRITE_SIZE scaled by a copy-kernel calibration), or
+    None when no summary exists for this workload/variant or the kernel source
+    changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash() or rec.get("variant") != variant:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
 def tri(lmax):
     return (lmax + 1) * (lmax + 2) // 2
 
@@ -107,13 +132,15 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="randoms3072", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32"])
     ap.add_argument("--points-per-lane", type=int, default=0)
     ap.add_argument("--l-block", type=int, default=0)
     ap.add_argument("--scale", type=float, default=1.0, help="catalog size factor (1 = the named workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter runs scale FETCH/WRITE_SIZE by it)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -132,11 +159,17 @@ def main():
     t0 = time.time()
     cats = make_catalogs(args.workload, args.scale)
     print(f"[bench] generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     dev = []
     for name, c in cats:
         dev.append((name, torch.as_tensor(c.theta).cuda(), torch.as_tensor(c.phi).cuda(),
                     torch.as_tensor(c.w).cuda(), c.n))
-    prec = ptalm.MIXED if args.precision == "mixed" else ptalm.FP64
+    prec = {"fp64": ptalm.FP64, "mixed": ptalm.MIXED, "fp32": ptalm.FP32}[args.precision]
     opt = ptalm.opts(precision=prec, points_per_lane=args.points_per_lane, l_block=args.l_block, timing=1)
     outs = [torch.empty(2 * T, dtype=torch.float64, device="cuda") for _ in dev]
     cls = [torch.empty(lmax + 1, dtype=torch.float64, device="cuda") for _ in range(2)]
@@ -156,7 +189,7 @@ def main():
         kernel_ms.append(ms)
 
     # build the per-lmax tables outside the timed region
-    ptalm.alm_from_points(dev[0][1][:1], dev[0][2][:1], dev[0][3][:1], lmax)
+    ptalm.prepare(lmax)
     torch.cuda.synchronize()
     for i in range(args.warmup):
         print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
@@ -177,15 +210,18 @@ def main():
     k_ms = float(np.mean(kernel_ms)) / len(dev)           # average transform-kernel launch
     flops_per_launch = FLOPS_PER_TERM * terms_per_step / len(dev)
     achieved = flops_per_launch / (k_ms * 1e-3) / 1e12
+    variant = f"kp={args.points_per_lane or 'default'},lb={args.l_block or 'default'},{args.precision}"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "alm_fp64_kernel" if prec == ptalm.FP64 else "alm_mixed_kernel",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(args.workload if args.scale == 1.0 else None, variant),
+                "kernel": "alm_direct_kernel<" + {"fp64": "double, double", "mixed": "double, float",
+                                                  "fp32": "float, float"}[args.precision] + ", ...>",
                 "kernel_ms_per_launch": round(k_ms, 3), "flops_per_term": FLOPS_PER_TERM}
 
     line = {"metric": METRIC, "value": value, "unit": UNIT,
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64" if prec == ptalm.FP64 else "f32+f64", "data": "synthetic",
+            "dtype": {"fp64": "f64", "mixed": "f64 recurrence + f32 products", "fp32": "f32 + f64"}[args.precision], "data": "synthetic",
             "config": {"workload": wl["desc"], "lmax": lmax, "points": sum(n for *_, n in dev),
                        "terms_per_step": terms_per_step, "precision": args.precision,
                        "points_per_lane": args.points_per_lane or "default", "l_block": args.l_block or "default"},

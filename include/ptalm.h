@@ -72,8 +72,12 @@ int ptalm_alm_from_points(const double *theta, const double *phi, const double *
 
 /* Arithmetic of the transform. */
 typedef enum {
-    PTALM_FP64 = 0,   /* recurrence and sums in FP64                                        */
-    PTALM_MIXED = 1   /* FP32 recurrence and products; FP64 trig, seed exponent, reductions */
+    PTALM_FP64 = 0,   /* recurrence, products and sums in FP64                                  */
+    PTALM_MIXED = 1,  /* FP64 recurrence; FP32 products, per-lane sums and cross-lane reduction;
+                         FP64 trig, seed exponent, phase and block partials                     */
+    PTALM_FP32 = 2    /* FP32 recurrence and products; FP64 trig, seed exponent, phase and block
+                         partials.  An FP32 recurrence carries x = cos(theta) to 2^-24, which
+                         costs ~l * 2^-24 relative per value at degree l                        */
 } ptalm_precision;
 
 /* Options of ptalm_alm_from_points_ex.  Zero-initialise, then set fields;
@@ -145,6 +149,11 @@ int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax
  * until that work has finished.  PTALM_EINVAL if no timed call was made.
  * Host only. */
 int ptalm_last_timing(double *transform_ms);
+
+/* Builds, on the current device, the coefficient tables the transform uses for
+ * this lmax (normally built on first use, synchronously).  Lets a caller keep
+ * that one-off cost out of a timed region or a latency-sensitive loop. */
+int ptalm_prepare(int lmax);
 
 /* Message of the last failed call on this thread ("" if none). Host only. */
 const char *ptalm_last_error(void);

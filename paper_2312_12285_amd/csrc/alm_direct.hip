@@ -1,4 +1,4 @@
-// FP64 direct point-to-harmonic transform: a_lm = sum_i w_i Y*_lm(theta_i, phi_i)
+// Direct point-to-harmonic transform: a_lm = sum_i w_i Y*_lm(theta_i, phi_i)
 // (eq. alm_def, Sec. 2.2) for 0 <= m <= l <= lmax.
 //
 // Work decomposition.  Points are cut into groups of 64*KP (KP points per
@@ -8,86 +8,116 @@
 // it walks its slice group by group and, for every m of its range, runs the
 // l-recurrence of App. A.1 for its 64*KP points in registers, accumulates the
 // per-l sums in registers over an l-block of LB values, reduces them across the
-// 64 lanes in a fixed order and adds them to its slice's partial a_lm column in
-// global memory.  The first group of a slice stores instead of adding, so no
-// clearing pass is needed.  A second kernel sums the S partials in slice order
-// and applies the per-(l, m) output scale.  Every reduction order is fixed, so
-// results are bitwise reproducible.
+// 64 lanes in a fixed order and adds them to its slice's partial a_lm column
+// (FP64) in global memory.  The first group of a slice stores instead of adding,
+// so no clearing pass is needed.  A second kernel sums the S partials in slice
+// order and applies the per-(l, m) output scale.  Every reduction order is
+// fixed, so results are bitwise reproducible.
 //
 // Per point the kernel carries
 //   Z = w s^m e^{-i m phi}  as a complex FP64 mantissa and an int exponent,
 //       advanced from m to m+1 by one complex multiply with u = s e^{-i phi}
 //       (angle addition) and renormalised every step;
 //   (Ehat, Ohat), the split recurrence of tables.hip (one FMA per odd step,
-//       one multiply + one FMA per even step);
+//       one multiply + one FMA per even step), in the recurrence type RecT;
 //   q = exponent applied to Z when forming the weights W = Z 2^q (even l) and
-//       V = x W (odd l).  Near the poles s^m underflows while the recurrence
-//       grows: then W is 0 (ldexp underflow) and the chain keeps growing until
-//       it is rescaled by a power of two, which raises q, until W re-enters the
-//       FP64 range.  Contributions dropped this way are below 2^-700 |w|.
+//       V = x W (odd l), in the product type AccT.  Near the poles s^m
+//       underflows while the recurrence grows: then W is 0 (ldexp underflow)
+//       and the chain keeps growing until it is rescaled by a power of two,
+//       which raises q, until W re-enters the range of AccT.  Contributions
+//       dropped this way are below 2^-700 |w| (FP64) or 2^-35 |w| (FP32).
 //
-// Per term (point, l, m) the inner loop issues 3.5 FP64 VALU instructions:
-// 1.5 for the recurrence and 2 FMAs into the l-block sums.  The cross-lane
-// reduction costs about one FP64 add per reduced value per lane, i.e. a
-// fraction ~2/(3.5 KP) of the inner loop, and moves 1 KB of LDS per value
-// (half with the register stage), which is what limits small KP.
+// Arithmetic types: FP64 form RecT = AccT = double.  Mixed form: FP64
+// recurrence, FP32 products, per-lane sums and cross-lane reduction, FP64
+// partials.  FP32 form: FP32 recurrence and products (FP64 trig, seed exponent,
+// phase and partials).  The trig, seed and phase are FP64 in every form.
+//
+// Per term (point, l, m) the inner loop issues 3.5 VALU instructions: 1.5 for
+// the recurrence and 2 FMAs into the l-block sums.  The cross-lane reduction
+// costs about one add per reduced value per lane, i.e. a fraction ~2/(3.5 KP)
+// of the inner loop, and moves 64*sizeof(AccT) bytes of LDS per value and lane
+// group (half with the register stage), which is what limits small KP.
+#include <type_traits>
+
 #include "ptalm_internal.h"
 
 namespace ptalm {
 
 namespace {
 
-constexpr double kRescaleAbove = 0x1p+64;  // chain values are renormalised past this
+// Read-only tables in the constant address space: uniform indices into them
+// compile to scalar loads (s_load), so the step coefficients live in SGPRs.
+template <typename T>
+using const_ptr = const T __attribute__((address_space(4))) *;
 
-// Read-only table pointer in the constant address space: uniform indices into
-// it compile to scalar loads (s_load), so the step coefficients live in SGPRs.
-typedef const double __attribute__((address_space(4))) *const_f64_ptr;
-
-__device__ inline double ldexp_d(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
-__device__ inline int frexp_exp(double x) { return __builtin_amdgcn_frexp_exp(x); }
+__device__ inline double ldexp_t(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
+__device__ inline float ldexp_t(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+__device__ inline int frexp_exp_t(double x) { return __builtin_amdgcn_frexp_exp(x); }
+__device__ inline int frexp_exp_t(float x) { return __builtin_amdgcn_frexp_expf(x); }
 
 // (re, im) * 2^-e so that max(|re|, |im|) lies in [0.5, 1); exponent += e.
 __device__ inline void renorm(double &re, double &im, int &exponent) {
     const double mx = fmax(fabs(re), fabs(im));
-    const int e = (mx != 0.0) ? frexp_exp(mx) : 0;
-    re = ldexp_d(re, -e);
-    im = ldexp_d(im, -e);
+    const int e = (mx != 0.0) ? frexp_exp_t(mx) : 0;
+    re = ldexp_t(re, -e);
+    im = ldexp_t(im, -e);
     exponent += e;
 }
+
+// Chain range control.  Over 64 steps the chain grows by less than 2^255 even
+// next to the poles at m ~ 3000; over 16 steps by less than 2^98 for any
+// m <= 16383.  FP64 chains are checked every 64 l against 2^64, FP32 chains
+// every 16 l against 2^16, so neither can overflow between checks.
+template <typename RecT> struct ChainRange;
+template <> struct ChainRange<double> {
+    static constexpr int every_l = 64;
+    static constexpr double above = 0x1p+64;
+};
+template <> struct ChainRange<float> {
+    static constexpr int every_l = 16;
+    static constexpr float above = 0x1p+16f;
+};
 
 // Cross-lane reduction of the per-lane l-block sums (V values per lane, value
 // v = 2k + c for l = jb + k and c = re/im).  Optional register stage (SWAP = 1):
 // v_permlane32_swap exchanges the upper half of value i with the lower half of
-// value i + V/2, so after one FP64 add each lane holds V/2 values summed over
-// two lanes.  The rest goes through LDS as a transpose: every lane writes its
+// value i + V/2, so after one add each lane holds V/2 values summed over two
+// lanes.  The rest goes through LDS as a transpose: every lane writes its
 // values, then P = 64/V lanes per value each add an interleaved share of the
 // entries and combine by DPP.  All orders are fixed.
 template <int V, int SWAP>
 struct Red {
-    static constexpr int NV = V >> SWAP;        // values per lane entering LDS
-    static constexpr int ENTRIES = 64 >> SWAP;  // lanes contributing to each value there
+    static constexpr int ENTRIES = 64 >> SWAP;  // lanes contributing to each value in LDS
     static constexpr int P = 64 / V;            // lanes combining one value at the end
-    static constexpr int ROW = ENTRIES + 1;     // padded LDS row (doubles)
-    static constexpr int BUF = V * ROW;         // doubles per LDS buffer
+    static constexpr int ROW = ENTRIES + 1;     // padded LDS row (elements)
+    static constexpr int BUF = V * ROW;         // elements per LDS buffer
 };
 
-// x from lane (lane ^ xor_mask) within each quad (DPP quad_perm), xor_mask 1 or 2
-__device__ inline double dpp_xor(double x, int xor_mask) {
-    const int lo = __double2loint(x), hi = __double2hiint(x);
-    if (xor_mask == 1)
-        return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false),
-                                __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false));
-    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false),
-                            __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false));
+// value from lane (lane ^ 1) or (lane ^ 2) within each quad (DPP quad_perm)
+template <int XOR>
+__device__ inline int dpp_xor_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, XOR == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int XOR>
+__device__ inline double dpp_xor(double x) {
+    return __hiloint2double(dpp_xor_i<XOR>(__double2hiint(x)), dpp_xor_i<XOR>(__double2loint(x)));
+}
+template <int XOR>
+__device__ inline float dpp_xor(float x) {
+    return __int_as_float(dpp_xor_i<XOR>(__float_as_int(x)));
 }
 
 // Lanes 0-31 get value a summed over lanes j and j+32; lanes 32-63 get value b
-// summed over lanes j-32 and j (v_permlane32_swap on both halves of each double).
+// summed over lanes j-32 and j (v_permlane32_swap on each 32-bit half).
 __device__ inline double swap32_add(double a, double b) {
     unsigned al = __double2loint(a), ah = __double2hiint(a), bl = __double2loint(b), bh = __double2hiint(b);
     auto lo = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
     auto hi = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
     return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ inline float swap32_add(float a, float b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // Orders LDS accesses of this wavefront (each workgroup is one wavefront, and
@@ -98,8 +128,8 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int V, int SWAP>
-__device__ inline void reduce_write(double *buf, const double (&vals)[V], int lane) {
+template <typename AccT, int V, int SWAP>
+__device__ inline void reduce_write(AccT *buf, const AccT (&vals)[V], int lane) {
     using R = Red<V, SWAP>;
     if constexpr (SWAP == 0) {
 #pragma unroll
@@ -108,33 +138,37 @@ __device__ inline void reduce_write(double *buf, const double (&vals)[V], int la
         const int half = lane >> 5;
 #pragma unroll
         for (int i = 0; i < V / 2; ++i) {
-            const double u = swap32_add(vals[i], vals[i + V / 2]);
+            const AccT u = swap32_add(vals[i], vals[i + V / 2]);
             buf[(i + half * (V / 2)) * R::ROW + (lane & 31)] = u;
         }
     }
 }
 
-template <int V, int SWAP>
-__device__ inline double reduce_finish(const double *buf, int v, int h) {
+template <typename AccT, int V, int SWAP>
+__device__ inline AccT reduce_finish(const AccT *buf, int v, int h) {
     using R = Red<V, SWAP>;
     static_assert(R::P <= 4, "at most 4 lanes per value");
-    double sum = buf[v * R::ROW + h];
+    AccT sum = buf[v * R::ROW + h];
 #pragma unroll
     for (int k = 1; k < R::ENTRIES / R::P; ++k) sum += buf[v * R::ROW + h + k * R::P];
-    if constexpr (R::P >= 2) sum += dpp_xor(sum, 1);
-    if constexpr (R::P >= 4) sum += dpp_xor(sum, 2);
+    if constexpr (R::P >= 2) sum += dpp_xor<1>(sum);
+    if constexpr (R::P >= 4) sum += dpp_xor<2>(sum);
     return sum;
 }
 
-template <int KP, int LB, int SWAP, int PIPE>
-__global__ __launch_bounds__(64) void alm_fp64_kernel(AlmArgs args) {
+template <typename RecT, typename AccT, int KP, int LB, int SWAP, int PIPE>
+__global__ __launch_bounds__(64) void alm_direct_kernel(AlmArgs args) {
     static_assert(LB % 2 == 0 && 64 % (2 * LB) == 0, "LB must be even and 2*LB must divide 64");
     constexpr int V = 2 * LB;  // values reduced per l-block (re, im per l)
     using R = Red<V, SWAP>;
     constexpr int P = R::P;
-    constexpr int RESCALE_EVERY = (64 / LB) > 0 ? (64 / LB) : 1;  // l-blocks between chain checks
+    // the chain is converted to AccT for the products, so it must stay inside the
+    // range of the narrower of the two types
+    using NarrowT = typename std::conditional<(sizeof(AccT) < sizeof(RecT)), AccT, RecT>::type;
+    constexpr int RESCALE_EVERY = (ChainRange<NarrowT>::every_l / LB) > 0 ? (ChainRange<NarrowT>::every_l / LB) : 1;
+    constexpr RecT kAbove = (RecT)ChainRange<NarrowT>::above;
 
-    __shared__ double red[(PIPE ? 2 : 1) * R::BUF];
+    __shared__ AccT red[(PIPE ? 2 : 1) * R::BUF];
 
     const int lane = threadIdx.x;
     const int lmax = args.lmax;
@@ -144,7 +178,8 @@ __global__ __launch_bounds__(64) void alm_fp64_kernel(AlmArgs args) {
     // step coefficients below are fetched with scalar loads
     const int m_a = __builtin_amdgcn_readfirstlane(args.range_m[r]);
     const int m_b = __builtin_amdgcn_readfirstlane(args.range_m[r + 1]);
-    const const_f64_ptr coef = (const_f64_ptr)args.coef;
+    const const_ptr<RecT> coef =
+        (const_ptr<RecT>)(sizeof(RecT) == 8 ? (const void *)args.coef : (const void *)args.coef32);
     const int64_t g_a = (int64_t)s * args.groups / args.n_slices;
     const int64_t g_b = (int64_t)(s + 1) * args.groups / args.n_slices;
     double *part = args.partial + (int64_t)s * 2 * tri_size(lmax);
@@ -173,8 +208,8 @@ __global__ __launch_bounds__(64) void alm_fp64_kernel(AlmArgs args) {
             double br = st * cp, bi = -st * sp;
             int be = 0;
             renorm(br, bi, be);
-            ur[t] = ldexp_d(br, be);  // u itself for the per-m step (|u| <= 1)
-            ui[t] = ldexp_d(bi, be);
+            ur[t] = ldexp_t(br, be);  // u itself for the per-m step (|u| <= 1)
+            ui[t] = ldexp_t(bi, be);
             // Z = w * u^{m_a} by binary powering with exponent tracking
             double rr = 1.0, ri = 0.0;
             int re = 0;
@@ -204,21 +239,23 @@ __global__ __launch_bounds__(64) void alm_fp64_kernel(AlmArgs args) {
 
         for (int m = m_a; m < m_b; ++m) {
             const int L = lmax - m + 1;  // number of l values of this order
-            const const_f64_ptr cm = coef + coef_segment(lmax, m);
+            const const_ptr<RecT> cm = coef + coef_segment(lmax, m);
             double *pm = part + 2 * column_start(lmax, m);
 
-            double E[KP], O[KP], y[KP], Wr[KP], Wi[KP], Vr[KP], Vi[KP];
+            RecT E[KP], O[KP], y[KP];
+            AccT Wr[KP], Wi[KP], Vr[KP], Vi[KP];
             int q[KP];
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
-                E[t] = -1.0;
-                O[t] = 0.0;
-                y[t] = x[t] * x[t];
+                E[t] = RecT(-1);
+                O[t] = RecT(0);
+                y[t] = (RecT)(x[t] * x[t]);
                 q[t] = Ze[t];
-                Wr[t] = ldexp_d(Zr[t], q[t]);
-                Wi[t] = ldexp_d(Zi[t], q[t]);
-                Vr[t] = Wr[t] * x[t];
-                Vi[t] = Wi[t] * x[t];
+                const double wr = ldexp_t(Zr[t], q[t]), wi = ldexp_t(Zi[t], q[t]);
+                Wr[t] = (AccT)wr;
+                Wi[t] = (AccT)wi;
+                Vr[t] = (AccT)(wr * x[t]);
+                Vi[t] = (AccT)(wi * x[t]);
             }
 
             // with the pipelined reduction the block finished now is the previous one
@@ -234,26 +271,28 @@ __global__ __launch_bounds__(64) void alm_fp64_kernel(AlmArgs args) {
                 double *dst = pm + 2 * jb + v;
                 double prev = 0.0;
                 if (owner && !first) prev = *dst;
-                double c[LB];
+                RecT c[LB];
 #pragma unroll
                 for (int k = 0; k < LB; ++k) c[k] = cm[jb + k];
-                double vals[V];
+                AccT vals[V];
 #pragma unroll
                 for (int k = 0; k < LB; ++k) {
-                    double ar = 0.0, ai = 0.0;
+                    AccT ar = AccT(0), ai = AccT(0);
                     if ((k & 1) == 0) {
 #pragma unroll
                         for (int t = 0; t < KP; ++t) {
                             E[t] = fma(c[k] * y[t], O[t], -E[t]);
-                            ar = fma(E[t], Wr[t], ar);
-                            ai = fma(E[t], Wi[t], ai);
+                            const AccT e = (AccT)E[t];
+                            ar = fma(e, Wr[t], ar);
+                            ai = fma(e, Wi[t], ai);
                         }
                     } else {
 #pragma unroll
                         for (int t = 0; t < KP; ++t) {
                             O[t] = fma(c[k], E[t], -O[t]);
-                            ar = fma(O[t], Vr[t], ar);
-                            ai = fma(O[t], Vi[t], ai);
+                            const AccT o = (AccT)O[t];
+                            ar = fma(o, Vr[t], ar);
+                            ai = fma(o, Vi[t], ai);
                         }
                     }
                     vals[2 * k] = ar;
@@ -263,42 +302,41 @@ __global__ __launch_bounds__(64) void alm_fp64_kernel(AlmArgs args) {
                 if constexpr (PIPE) {
                     if (pending) {
                         wave_lds_sync();
-                        const double sum = reduce_finish<V, SWAP>(red + (cur ^ 1) * R::BUF, v, h);
-                        if (p_owner) *p_dst = p_prev + sum;
+                        const AccT sum = reduce_finish<AccT, V, SWAP>(red + (cur ^ 1) * R::BUF, v, h);
+                        if (p_owner) *p_dst = p_prev + (double)sum;
                     }
-                    reduce_write<V, SWAP>(red + cur * R::BUF, vals, lane);
+                    reduce_write<AccT, V, SWAP>(red + cur * R::BUF, vals, lane);
                     pending = true;
                     p_owner = owner;
                     p_dst = dst;
                     p_prev = prev;
                     cur ^= 1;
                 } else {
-                    reduce_write<V, SWAP>(red, vals, lane);
+                    reduce_write<AccT, V, SWAP>(red, vals, lane);
                     wave_lds_sync();
-                    const double sum = reduce_finish<V, SWAP>(red, v, h);
-                    if (owner) *dst = prev + sum;
+                    const AccT sum = reduce_finish<AccT, V, SWAP>(red, v, h);
+                    if (owner) *dst = prev + (double)sum;
                     wave_lds_sync();
                 }
 
-                // ---- keep the chain inside the FP64 range ----------------------
-                // Growth over 64 steps stays below 2^255 even next to the poles
-                // at m ~ 3000, so checking every 64 l against 2^64 cannot overflow.
+                // ---- keep the chain inside the range of RecT -------------------
                 if ((blk % RESCALE_EVERY) == RESCALE_EVERY - 1) {
                     bool big = false;
 #pragma unroll
-                    for (int t = 0; t < KP; ++t) big |= fmax(fabs(E[t]), fabs(O[t])) > kRescaleAbove;
+                    for (int t = 0; t < KP; ++t) big |= fmax(fabs(E[t]), fabs(O[t])) > kAbove;
                     if (__any(big)) {
 #pragma unroll
                         for (int t = 0; t < KP; ++t) {
-                            const double mx = fmax(fabs(E[t]), fabs(O[t]));
-                            const int e = (mx > kRescaleAbove) ? frexp_exp(mx) : 0;
-                            E[t] = ldexp_d(E[t], -e);
-                            O[t] = ldexp_d(O[t], -e);
+                            const RecT mx = fmax(fabs(E[t]), fabs(O[t]));
+                            const int e = (mx > kAbove) ? frexp_exp_t(mx) : 0;
+                            E[t] = ldexp_t(E[t], -e);
+                            O[t] = ldexp_t(O[t], -e);
                             q[t] += e;
-                            Wr[t] = ldexp_d(Zr[t], q[t]);
-                            Wi[t] = ldexp_d(Zi[t], q[t]);
-                            Vr[t] = Wr[t] * x[t];
-                            Vi[t] = Wi[t] * x[t];
+                            const double wr = ldexp_t(Zr[t], q[t]), wi = ldexp_t(Zi[t], q[t]);
+                            Wr[t] = (AccT)wr;
+                            Wi[t] = (AccT)wi;
+                            Vr[t] = (AccT)(wr * x[t]);
+                            Vi[t] = (AccT)(wi * x[t]);
                         }
                     }
                 }
@@ -306,8 +344,8 @@ __global__ __launch_bounds__(64) void alm_fp64_kernel(AlmArgs args) {
             if constexpr (PIPE) {
                 if (pending) {
                     wave_lds_sync();
-                    const double sum = reduce_finish<V, SWAP>(red + (cur ^ 1) * R::BUF, v, h);
-                    if (p_owner) *p_dst = p_prev + sum;
+                    const AccT sum = reduce_finish<AccT, V, SWAP>(red + (cur ^ 1) * R::BUF, v, h);
+                    if (p_owner) *p_dst = p_prev + (double)sum;
                     wave_lds_sync();
                 }
             }
@@ -339,35 +377,72 @@ __global__ void reduce_partials_kernel(const double *__restrict__ partial, int n
     }
 }
 
-template <int KP, int LB, int SWAP, int PIPE>
+template <typename RecT, typename AccT, int KP, int LB, int SWAP, int PIPE>
 hipError_t launch_one(const AlmArgs &a, hipStream_t stream) {
     const int blocks = a.n_ranges * a.n_slices;
-    hipLaunchKernelGGL((alm_fp64_kernel<KP, LB, SWAP, PIPE>), dim3(blocks), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL((alm_direct_kernel<RecT, AccT, KP, LB, SWAP, PIPE>), dim3(blocks), dim3(64), 0, stream, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Compiled variants: (points per lane, l-block, register stage, pipelined reduction).
+// Compiled variants: (points per lane, l-block, register stage, pipelined reduction),
 // mode = register stage | pipelined << 1.
 #define PTALM_FP64_VARIANTS(X)                                                                    \
     X(6, 8, 0, 0) X(7, 8, 0, 0) X(6, 16, 0, 0) X(6, 16, 1, 0) X(6, 16, 1, 1) X(6, 16, 0, 1)     \
     X(5, 16, 1, 1) X(8, 16, 1, 1) X(10, 16, 1, 1) X(12, 16, 1, 1) X(12, 16, 0, 1) X(14, 8, 0, 1) \
-    X(14, 8, 1, 1) X(12, 8, 1, 1) X(4, 8, 0, 0) X(8, 32, 0, 0) X(16, 8, 0, 0)
+    X(14, 8, 1, 1) X(12, 8, 1, 1) X(4, 8, 0, 0) X(8, 32, 0, 0) X(16, 8, 0, 0) X(7, 8, 1, 1)     \
+    X(8, 8, 1, 1) X(6, 8, 1, 1) X(7, 16, 1, 1)
+
+// Mixed (FP64 recurrence, FP32 products) and FP32 (FP32 recurrence) variants.
+#define PTALM_MIXED_VARIANTS(X) X(6, 16, 1, 1) X(7, 16, 1, 1) X(8, 16, 1, 1) X(8, 8, 1, 1) X(10, 8, 1, 1)
+#define PTALM_FP32_VARIANTS(X) X(8, 16, 1, 1) X(10, 16, 1, 1) X(12, 16, 1, 1) X(12, 8, 1, 1) X(14, 8, 1, 1)
+
+#define PTALM_MATCH(K, L, S, P) (kp == K && lb == L && mode == (S | (P << 1)))
 
 bool fp64_variant_exists(int kp, int lb, int mode) {
-#define X(K, L, S, P) \
-    if (kp == K && lb == L && mode == (S | (P << 1))) return true;
+#define X(K, L, S, P) if (PTALM_MATCH(K, L, S, P)) return true;
     PTALM_FP64_VARIANTS(X)
+#undef X
+    return false;
+}
+
+bool mixed_variant_exists(int kp, int lb, int mode) {
+#define X(K, L, S, P) if (PTALM_MATCH(K, L, S, P)) return true;
+    PTALM_MIXED_VARIANTS(X)
+#undef X
+    return false;
+}
+
+bool fp32_variant_exists(int kp, int lb, int mode) {
+#define X(K, L, S, P) if (PTALM_MATCH(K, L, S, P)) return true;
+    PTALM_FP32_VARIANTS(X)
 #undef X
     return false;
 }
 
 hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported) {
     *supported = true;
-#define X(K, L, S, P) \
-    if (kp == K && lb == L && mode == (S | (P << 1))) return launch_one<K, L, S, P>(a, stream);
+#define X(K, L, S, P) if (PTALM_MATCH(K, L, S, P)) return launch_one<double, double, K, L, S, P>(a, stream);
     PTALM_FP64_VARIANTS(X)
+#undef X
+    *supported = false;
+    return hipSuccess;
+}
+
+hipError_t launch_alm_mixed(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported) {
+    *supported = true;
+#define X(K, L, S, P) if (PTALM_MATCH(K, L, S, P)) return launch_one<double, float, K, L, S, P>(a, stream);
+    PTALM_MIXED_VARIANTS(X)
+#undef X
+    *supported = false;
+    return hipSuccess;
+}
+
+hipError_t launch_alm_fp32(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported) {
+    *supported = true;
+#define X(K, L, S, P) if (PTALM_MATCH(K, L, S, P)) return launch_one<float, float, K, L, S, P>(a, stream);
+    PTALM_FP32_VARIANTS(X)
 #undef X
     *supported = false;
     return hipSuccess;

@@ -133,6 +133,8 @@ int get_ranges(int lmax, int R, const int **out) {
 constexpr int kDefaultKP = 6;
 constexpr int kDefaultLB = 16;
 constexpr int kDefaultMode = 3;  // register butterfly stage + pipelined reduction
+constexpr int kMixedKP = 8;   // 238 VGPRs: two wavefronts per SIMD
+constexpr int kFp32KP = 10;
 constexpr int kTargetItems = 8192;   // (slice, range) items: ~4 per resident wavefront
 constexpr int kMaxSlices = 32;
 
@@ -147,16 +149,19 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     if (!o) o = &d;
     r->precision = o->precision;
     r->n_weights = o->n_weights > 0 ? o->n_weights : 1;
-    if (o->precision != PTALM_FP64 && o->precision != PTALM_MIXED) return fail(PTALM_EINVAL, "bad precision");
+    if (o->precision != PTALM_FP64 && o->precision != PTALM_MIXED && o->precision != PTALM_FP32)
+        return fail(PTALM_EINVAL, "bad precision");
     if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0 ||
         o->reduction < 0 || o->reduction > 4)
         return fail(PTALM_EINVAL, "option out of range");
     if (o->n_slices > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
-    r->kp = o->points_per_lane ? o->points_per_lane : kDefaultKP;
+    const int def_kp = r->precision == PTALM_FP64 ? kDefaultKP : (r->precision == PTALM_MIXED ? kMixedKP : kFp32KP);
+    r->kp = o->points_per_lane ? o->points_per_lane : def_kp;
     r->lb = o->l_block ? o->l_block : kDefaultLB;
     r->mode = o->reduction ? o->reduction - 1 : kDefaultMode;
-    const bool have = (r->precision == PTALM_FP64) ? ptalm::fp64_variant_exists(r->kp, r->lb, r->mode)
-                                                   : ptalm::mixed_variant_exists(r->kp, r->lb, r->mode);
+    const bool have = r->precision == PTALM_FP64    ? ptalm::fp64_variant_exists(r->kp, r->lb, r->mode)
+                      : r->precision == PTALM_MIXED ? ptalm::mixed_variant_exists(r->kp, r->lb, r->mode)
+                                                    : ptalm::fp32_variant_exists(r->kp, r->lb, r->mode);
     if (!have) return fail(PTALM_ENOTSUP, "no kernel variant with these points_per_lane / l_block / reduction");
     r->groups = (n + 64 * r->kp - 1) / (64 * r->kp);
     int64_t S = o->n_slices ? o->n_slices : std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, r->groups));
@@ -262,8 +267,9 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
             rc = fail_hip(e, "hipEventRecord");
             break;
         }
-        e = (r.precision == PTALM_FP64) ? ptalm::launch_alm_fp64(a, r.kp, r.lb, r.mode, stream, &supported)
-                                        : ptalm::launch_alm_mixed(a, r.kp, r.lb, r.mode, stream, &supported);
+        e = r.precision == PTALM_FP64    ? ptalm::launch_alm_fp64(a, r.kp, r.lb, r.mode, stream, &supported)
+            : r.precision == PTALM_MIXED ? ptalm::launch_alm_mixed(a, r.kp, r.lb, r.mode, stream, &supported)
+                                         : ptalm::launch_alm_fp32(a, r.kp, r.lb, r.mode, stream, &supported);
         if (timed && v == r.n_weights - 1 && e == hipSuccess && supported) {
             hipError_t e2 = hipEventRecord(g_timing.stop, stream);
             if (e2 != hipSuccess) e = e2;
@@ -321,6 +327,13 @@ int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax
         if (p != nullptr && (p == alm_data || p == alm_randoms)) return fail(PTALM_EINVAL, "output aliases an input");
     hipError_t e = ptalm::launch_fkp(alm_data, alm_randoms, lmax, delta, window, alpha_out, (hipStream_t)stream);
     return e == hipSuccess ? PTALM_OK : fail_hip(e, "fkp kernel launch");
+}
+
+int ptalm_prepare(int lmax) {
+    g_error.clear();
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    const ptalm::Tables *tab;
+    return get_tables(lmax, &tab);
 }
 
 int ptalm_release_cache(void) {

@@ -72,6 +72,7 @@ struct AlmArgs {
 hipError_t build_tables(int lmax, Tables *t, hipStream_t stream);
 hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
 hipError_t launch_alm_mixed(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
+hipError_t launch_alm_fp32(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
 hipError_t launch_reduce_partials(const double *partial, int n_slices, const double *sigma, int lmax,
                                   double *alm, hipStream_t stream);
 hipError_t launch_cl(const double *alm1, const double *alm2, int lmax, double *cl, hipStream_t stream);
@@ -83,5 +84,6 @@ hipError_t launch_fkp(const double *ad, const double *ar, int lmax, double *delt
 // with mode = register butterfly stage (bit 0) | pipelined reduction (bit 1).
 bool fp64_variant_exists(int kp, int lb, int mode);
 bool mixed_variant_exists(int kp, int lb, int mode);
+bool fp32_variant_exists(int kp, int lb, int mode);
 
 }  // namespace ptalm

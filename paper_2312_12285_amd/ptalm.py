@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 PTALM_OK, PTALM_EINVAL, PTALM_ENOMEM, PTALM_EDEVICE, PTALM_EBUSY, PTALM_ENOTSUP = 0, -1, -2, -3, -4, -5
-FP64, MIXED = 0, 1
+FP64, MIXED, FP32 = 0, 1, 2
 LMAX_MAX = 16383
 
 _vp = ctypes.c_void_p
@@ -56,6 +56,7 @@ _fkp = _sig("ptalm_fkp_fields", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp,
 _last_error = _sig("ptalm_last_error", ctypes.c_char_p, [])
 _last_timing = _sig("ptalm_last_timing", ctypes.c_int, [ctypes.POINTER(ctypes.c_double)])
 _release = _sig("ptalm_release_cache", ctypes.c_int, [])
+_prepare = _sig("ptalm_prepare", ctypes.c_int, [ctypes.c_int])
 _plan_ranges = _sig("ptalm_plan_m_ranges", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
 
 
@@ -181,6 +182,11 @@ def fkp_fields(alm_data, alm_randoms, lmax: int, stream=None):
     alpha = torch.empty(1, dtype=torch.float64, device=alm_data.device)
     _check(_fkp(_ptr(alm_data), _ptr(alm_randoms), lmax, _ptr(delta), _ptr(window), _ptr(alpha), _stream(stream)))
     return delta, window, alpha
+
+
+def prepare(lmax: int):
+    """Build the per-lmax coefficient tables on the current device ahead of first use."""
+    _check(_prepare(lmax))
 
 
 def release_cache():

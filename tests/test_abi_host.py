@@ -83,7 +83,7 @@ def test_workspace_bytes_matches_plan(lib):
     assert lib.ptalm_workspace_bytes(10 ** 8, 3072, ctypes.byref(o)) == 16 * 2 * T * 8
     o = Opts(0, 1, 6, 16, 0, 0, 0, 0)    # auto slices, clamped to the number of point groups (1 here)
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 1 * 2 * (65 * 66 // 2) * 8
-    o = Opts(0, 1, 7, 16, 0, 0, 0, 0)    # no such kernel variant
+    o = Opts(0, 1, 9, 16, 0, 0, 0, 0)    # no such kernel variant
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0
     o = Opts(5, 1, 0, 0, 0, 0, 0, 0)    # bad precision
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0

@@ -75,7 +75,8 @@ def test_fullsky_lmax64_n1e4(lib, oracle):
 
 FP64_VARIANTS = [(6, 8, 0, 0), (7, 8, 0, 0), (6, 16, 0, 0), (6, 16, 1, 0), (6, 16, 1, 1), (6, 16, 0, 1),
                  (5, 16, 1, 1), (8, 16, 1, 1), (10, 16, 1, 1), (12, 16, 1, 1), (12, 16, 0, 1), (14, 8, 0, 1),
-                 (14, 8, 1, 1), (12, 8, 1, 1), (4, 8, 0, 0), (8, 32, 0, 0), (16, 8, 0, 0)]
+                 (14, 8, 1, 1), (12, 8, 1, 1), (4, 8, 0, 0), (8, 32, 0, 0), (16, 8, 0, 0), (7, 8, 1, 1), (8, 8, 1, 1),
+                 (6, 8, 1, 1), (7, 16, 1, 1)]
 
 
 @pytest.mark.parametrize("kp,lb,swap,pipe", FP64_VARIANTS)
