@@ -75,9 +75,13 @@ typedef enum {
     PTALM_FP64 = 0,   /* recurrence, products and sums in FP64                                  */
     PTALM_MIXED = 1,  /* FP64 recurrence; FP32 products, per-lane sums and cross-lane reduction;
                          FP64 trig, seed exponent, phase and block partials                     */
-    PTALM_FP32 = 2    /* FP32 recurrence and products; FP64 trig, seed exponent, phase and block
+    PTALM_FP32 = 2,   /* FP32 recurrence and products; FP64 trig, seed exponent, phase and block
                          partials.  An FP32 recurrence carries x = cos(theta) to 2^-24, which
                          costs ~l * 2^-24 relative per value at degree l                        */
+    PTALM_BF16X3 = 3  /* multi-weight only (n_weights 16 or 32): FP64 recurrence; the sum over
+                         points as a matrix product on the matrix cores with bf16 hi+lo split
+                         operands, three products (hi.hi + hi.lo + lo.hi), FP32 accumulation,
+                         FP64 final sum: ~1e-5 relative per product                             */
 } ptalm_precision;
 
 /* Options of ptalm_alm_from_points_ex.  Zero-initialise, then set fields;

@@ -149,8 +149,24 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     if (!o) o = &d;
     r->precision = o->precision;
     r->n_weights = o->n_weights > 0 ? o->n_weights : 1;
-    if (o->precision != PTALM_FP64 && o->precision != PTALM_MIXED && o->precision != PTALM_FP32)
+    if (o->precision != PTALM_FP64 && o->precision != PTALM_MIXED && o->precision != PTALM_FP32 &&
+        o->precision != PTALM_BF16X3)
         return fail(PTALM_EINVAL, "bad precision");
+    if (o->precision == PTALM_BF16X3) {
+        if (!ptalm::multi_nw_supported(r->n_weights))
+            return fail(PTALM_ENOTSUP, "the split-bf16 MFMA form needs n_weights 16 or 32");
+        r->kp = 0;
+        r->lb = 0;
+        r->mode = 0;
+        r->groups = (n + 255) / 256;
+        const int64_t want = (512 + lmax) / (lmax + 1);
+        int64_t S = o->n_slices ? o->n_slices : want;
+        if (S > std::max<int64_t>(1, r->groups)) S = std::max<int64_t>(1, r->groups);
+        if (S > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
+        r->S = (int)S;
+        r->R = lmax + 1;
+        return PTALM_OK;
+    }
     if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0 ||
         o->reduction < 0 || o->reduction > 4)
         return fail(PTALM_EINVAL, "option out of range");
@@ -173,8 +189,18 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     return PTALM_OK;
 }
 
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 size_t partial_bytes(const Resolved &r, int lmax) {
     return sizeof(double) * 2 * (size_t)ptalm::tri_size(lmax) * (size_t)r.S;
+}
+
+// multi-weight MFMA scratch: FP32 partials [S][NW][2T], then the FP32 weight copy
+size_t multi_partial_bytes(const Resolved &r, int lmax) {
+    return align256(sizeof(float) * 2 * (size_t)ptalm::tri_size(lmax) * (size_t)r.n_weights * (size_t)r.S);
+}
+size_t multi_bytes(const Resolved &r, int64_t n, int lmax) {
+    return multi_partial_bytes(r, lmax) + align256(sizeof(float) * (size_t)n * (size_t)r.n_weights);
 }
 
 }  // namespace
@@ -205,7 +231,7 @@ size_t ptalm_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts) {
     if (n < 0 || !lmax_ok(lmax)) return 0;
     Resolved r;
     if (resolve(n, lmax, opts, &r)) return 0;
-    return partial_bytes(r, lmax);
+    return r.precision == PTALM_BF16X3 ? multi_bytes(r, n, lmax) : partial_bytes(r, lmax);
 }
 
 int ptalm_alm_from_points_ex(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
@@ -219,7 +245,7 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
     Resolved r;
     int rc = resolve(n, lmax, opts, &r);
     if (rc) return rc;
-    const size_t need = partial_bytes(r, lmax);
+    const size_t need = r.precision == PTALM_BF16X3 ? multi_bytes(r, n, lmax) : partial_bytes(r, lmax);
     if (workspace != nullptr && ws_bytes < need) return fail(PTALM_EINVAL, "workspace too small");
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t T = ptalm::tri_size(lmax);
@@ -233,18 +259,46 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
     const int *ranges;
     if ((rc = get_ranges(lmax, r.R, &ranges))) return rc;
 
-    double *partial = (double *)workspace;
-    bool own = false;
-    if (partial == nullptr) {
-        e = hipMallocAsync((void **)&partial, need, stream);
-        if (e != hipSuccess) return fail_hip(e, "hipMallocAsync(partial)");
-        own = true;
-    }
     const bool timed = opts != nullptr && opts->timing != 0;
     if (timed) {
         g_timing.valid = false;
         if (!g_timing.start && (e = hipEventCreate(&g_timing.start)) != hipSuccess) return fail_hip(e, "hipEventCreate");
         if (!g_timing.stop && (e = hipEventCreate(&g_timing.stop)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+    }
+    double *partial = (double *)workspace;
+    bool own = false;
+    if (partial == nullptr) {
+        e = hipMallocAsync((void **)&partial, need, stream);
+        if (e != hipSuccess) return fail_hip(e, "hipMallocAsync(scratch)");
+        own = true;
+    }
+    if (r.precision == PTALM_BF16X3) {
+        ptalm::MultiArgs ma;
+        ma.theta = theta;
+        ma.phi = phi;
+        ma.w = w;
+        ma.partial32 = (float *)partial;
+        ma.w32 = (float *)((char *)partial + multi_partial_bytes(r, lmax));
+        ma.n = n;
+        ma.lmax = lmax;
+        ma.n_weights = r.n_weights;
+        ma.n_slices = r.S;
+        ma.groups = r.groups;
+        ma.coef = tab->coef;
+        if (timed && (e = hipEventRecord(g_timing.start, stream)) != hipSuccess) rc = fail_hip(e, "hipEventRecord");
+        if (rc == PTALM_OK && (e = ptalm::launch_alm_multi(ma, stream)) != hipSuccess)
+            rc = fail_hip(e, "multi-weight kernel launch");
+        if (rc == PTALM_OK && timed) {
+            if ((e = hipEventRecord(g_timing.stop, stream)) != hipSuccess) rc = fail_hip(e, "hipEventRecord");
+            else g_timing.valid = true;
+        }
+        if (rc == PTALM_OK && (e = ptalm::launch_multi_finish(ma, tab->sigma, alm, stream)) != hipSuccess)
+            rc = fail_hip(e, "multi-weight finish launch");
+        if (own) {
+            e = hipFreeAsync(partial, stream);
+            if (e != hipSuccess && rc == PTALM_OK) rc = fail_hip(e, "hipFreeAsync(scratch)");
+        }
+        return rc;
     }
     for (int v = 0; v < r.n_weights && rc == PTALM_OK; ++v) {
         ptalm::AlmArgs a;

@@ -68,6 +68,21 @@ struct AlmArgs {
     int n_weights;
 };
 
+// Arguments of the multi-weight MFMA kernels.
+struct MultiArgs {
+    const double *theta;
+    const double *phi;
+    const double *w;          // device, n_weights rows of n
+    float *w32;               // device scratch, FP32 copy of w
+    int64_t n;
+    int lmax;
+    int n_weights;            // 16 or 32
+    int n_slices;
+    int64_t groups;           // ceil(n / 256)
+    const double *coef;       // device step coefficients
+    float *partial32;         // device, n_slices * n_weights * 2T floats
+};
+
 // --- launchers (defined in the .hip files) ----------------------------------
 hipError_t build_tables(int lmax, Tables *t, hipStream_t stream);
 hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
@@ -85,5 +100,9 @@ hipError_t launch_fkp(const double *ad, const double *ar, int lmax, double *delt
 bool fp64_variant_exists(int kp, int lb, int mode);
 bool mixed_variant_exists(int kp, int lb, int mode);
 bool fp32_variant_exists(int kp, int lb, int mode);
+
+bool multi_nw_supported(int nw);
+hipError_t launch_alm_multi(const MultiArgs &a, hipStream_t stream);
+hipError_t launch_multi_finish(const MultiArgs &a, const double *sigma, double *alm, hipStream_t stream);
 
 }  // namespace ptalm

@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 PTALM_OK, PTALM_EINVAL, PTALM_ENOMEM, PTALM_EDEVICE, PTALM_EBUSY, PTALM_ENOTSUP = 0, -1, -2, -3, -4, -5
-FP64, MIXED, FP32 = 0, 1, 2
+FP64, MIXED, FP32, BF16X3 = 0, 1, 2, 3
 LMAX_MAX = 16383
 
 _vp = ctypes.c_void_p
