@@ -10,19 +10,28 @@
 // accumulated in FP32 on v_mfma_f32_16x16x32_bf16; the neglected lo.lo term and
 // the residual of the two-term split leave ~2^-16 relative error per product.
 //
-// Work decomposition.  One workgroup (4 wavefronts, 256 threads) per (slice, m)
-// item, dispatched in increasing m (largest work first).  It streams its slice
-// in groups of 256 points, one point per thread:
+// Work decomposition.  One workgroup (8 wavefronts, 512 threads, one per compute
+// unit) per (slice, m) item, dispatched in increasing m (largest work first).  It
+// streams its slice in groups of 512 points, one point per thread:
 //   1. each thread computes its point's x, s^m e^{-i m phi} (FP64, exponent
-//      tracked) and writes its row of B (2 NW columns, bf16 hi/lo) to LDS;
-//      each wavefront then keeps its B fragments in registers for all l;
+//      tracked) and stages its row of B (FP32) and x in LDS; each wavefront
+//      then splits the B fragments of its half of the points (256) into bf16
+//      hi/lo registers kept for all l;
 //   2. per tile of 32 l: each thread advances the FP64 split recurrence of
-//      tables.hip 32 steps and writes A (bf16 hi/lo) for its point to LDS;
-//      wavefront w multiplies M-tile (w & 1) by its half of the N-tiles over the
-//      256 points (8 K-steps x 3 products per D tile) and adds the FP32 D tile
-//      into its slice's FP32 partial (the first group stores).
-// A final pass sums the slices in FP64 in fixed order and applies the output
-// scale sigma_lm.  Every order is fixed, so results are reproducible.
+//      tables.hip 32 steps and writes A (bf16 hi/lo) for its point to LDS, the
+//      16 even-l rows first, then the 16 odd-l rows.  An odd-l value of the
+//      recurrence lacks a factor x, which the wavefronts that own the odd rows
+//      fold into their copy of B instead.  Wavefront w multiplies M-tile
+//      (w & 1) by N-tiles of its quarter of the columns over the 256 points of
+//      its half (8 K-steps x 3 products per D tile), interleaved with the
+//      recurrence of the next tile.  The two wavefronts that hold the same D
+//      block for the two point halves exchange half of it through LDS; each adds
+//      its half of the block for all 512 points into the slice's FP32 partial
+//      (read-modify-write, the first group of a slice stores).
+// The partial buffer pads every order by 32 rows, so whole tiles are read and
+// written without bounds tests.  A final pass sums the slices in FP64 in fixed
+// order and applies the output scale sigma_lm.  Every order is fixed, so
+// results are reproducible.
 #include "ptalm_internal.h"
 
 namespace ptalm {
@@ -30,16 +39,21 @@ namespace ptalm {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16_bits;
 
 template <typename T>
 using const_ptr = const T __attribute__((address_space(4))) *;
 
-constexpr int kG = 256;          // points per group = threads per workgroup
+constexpr int kG = kMultiGroup;  // points per group = threads per workgroup
+constexpr int kHalf = kG / 2;    // points of one half: the K range of one wavefront
 constexpr int kLT = 32;          // l values per tile
-constexpr int kRow = kG + 8;     // padded LDS row (bf16 elements): rows land on different banks
+constexpr int kRowA = kG + 8;    // padded LDS row of an A tile (bf16): rows land on different banks
+constexpr int kRowB = kG + 4;    // padded LDS column of the staged B (floats)
 constexpr double kChainAbove = 0x1p+64;
+static_assert(kLT == kMultiPad, "tiles must fit the padding of the partial buffer");
 
 __device__ inline double ldexp_d(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
 __device__ inline int frexp_exp_d(double x) { return __builtin_amdgcn_frexp_exp(x); }
@@ -52,56 +66,81 @@ __device__ inline void renorm(double &re, double &im, int &exponent) {
     exponent += e;
 }
 
-// f = hi + lo + O(2^-16 |f|), both rounded to nearest even (v_cvt_pk_bf16_f32)
-__device__ inline void split_bf16(float f, bf16_bits &hi, bf16_bits &lo) {
-    const __bf16 h = (__bf16)f;
-    const __bf16 l = (__bf16)(f - (float)h);
-    hi = __builtin_bit_cast(bf16_bits, h);
-    lo = __builtin_bit_cast(bf16_bits, l);
+// An FP32 value the optimiser may not look through: the A operand is rounded to
+// FP32 first and then split, and must not be re-derived from the FP64 value.
+__device__ inline float opaque(float f) {
+    asm("" : "+v"(f));
+    return f;
+}
+
+// f_k = hi_k + lo_k + O(2^-17 |f_k|) for a pair (k = 0, 1), both parts rounded
+// to nearest even by v_cvt_pk_bf16_f32; the parts come back packed, element 0
+// in the low half.
+__device__ inline void split_pair(float f0, float f1, unsigned &hi, unsigned &lo) {
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){f0, f1}, bf16x2));
+    const float h0 = __builtin_bit_cast(float, hi << 16);
+    const float h1 = __builtin_bit_cast(float, hi & 0xffff0000u);
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){f0 - h0, f1 - h1}, bf16x2));
 }
 
 __device__ inline bf16x8 load_frag(const bf16_bits *p) {
     // 8 consecutive bf16 (16 bytes, 16-byte aligned)
-    const uint4 u = *reinterpret_cast<const uint4 *>(p);
-    bf16x8 r;
-    __builtin_memcpy(&r, &u, sizeof(r));
-    return r;
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
 }
 
 template <int NW>
-__global__ __launch_bounds__(256) void alm_multi_kernel(MultiArgs a) {
+__global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void alm_multi_kernel(MultiArgs a) {
     constexpr int NC = 2 * NW;          // columns of B (re, im per weight vector)
     constexpr int NT = NC / 16;         // 16-column N-tiles
-    constexpr int NTW = NT / 2;         // N-tiles per wavefront (two wavefronts per M-tile)
+    constexpr int NTW = NT / 2;         // N-tiles per wavefront (two wavefronts per M-tile and half)
+    constexpr int KS = kHalf / 32;      // K-steps of one wavefront per tile
+    constexpr int NV = 4 * NTW;         // D values per lane (value v = 4 n + r)
+    constexpr int NOWN = NV / 2;        // of which this wavefront adds into the partial
     static_assert(NW % 16 == 0 && NW <= 32, "NW must be 16 or 32");
-
-    __shared__ __attribute__((aligned(16))) bf16_bits Bh[NC * kRow];
-    __shared__ __attribute__((aligned(16))) bf16_bits Bl[NC * kRow];
-    __shared__ __attribute__((aligned(16))) bf16_bits Ah[2][kLT * kRow];   // double-buffered A tile
-    __shared__ __attribute__((aligned(16))) bf16_bits Al[2][kLT * kRow];
+    // LDS: one region used first as the FP32 staging of B and x at a group's
+    // start, then as the two A tiles (double buffer) x (hi, lo); after it the
+    // D exchange [tile parity][wavefront][value][lane]
+    constexpr int kStage = (NC * kRowB + kG) * 4;
+    constexpr int kATile = kLT * kRowA;                 // bf16 elements of one A part
+    constexpr int kABytes = 2 * 2 * kATile * 2;
+    constexpr int kMain = kStage > kABytes ? kStage : kABytes;
+    constexpr int kXch = 2 * (kG / 64) * NOWN * 64 * 4;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kMain + kXch];
+    float *Bs = reinterpret_cast<float *>(smem);        // [NC][kRowB]
+    float *Xs = Bs + NC * kRowB;                        // [kG]
+    bf16_bits *At = reinterpret_cast<bf16_bits *>(smem);  // [buffer][hi, lo][kLT][kRowA]
+    float *xch = reinterpret_cast<float *>(smem + kMain);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lmax = a.lmax;
     const int s = blockIdx.x % a.n_slices;
     const int m = __builtin_amdgcn_readfirstlane(blockIdx.x / a.n_slices);
     const int L = lmax - m + 1;
-    const int64_t T = tri_size(lmax);
     const int64_t g_a = (int64_t)s * a.groups / a.n_slices;
     const int64_t g_b = (int64_t)(s + 1) * a.groups / a.n_slices;
     const const_ptr<double> cm = (const_ptr<double>)a.coef + coef_segment(lmax, m);
-    float *part = a.partial32 + (int64_t)s * NW * 2 * T;
-    const int64_t col0 = column_start(lmax, m);
 
-    const int mt = wave & 1;             // M-tile of this wavefront
-    const int nt0 = (wave >> 1) * NTW;   // first N-tile of this wavefront
+    const int half = wave >> 2;          // point half of this wavefront (its K range)
+    const int kbase = half * kHalf;
+    const int mt = wave & 1;             // M-tile: 0 even l, 1 odd l
+    const int nt0 = ((wave >> 1) & 1) * NTW;   // first N-tile
+    const int partner = wave ^ 4;        // same D block, other point half
     const int frow = lane & 15;          // fragment row / column within a 16-tile
     const int fk = 8 * (lane >> 4);      // fragment k offset within a 32-step
+    // this lane's D rows: tile row 4*(lane/16) + r holds l = jb + 2*(4*(lane/16) + r) + mt
+    const int drow = 2 * (4 * (lane >> 4)) + mt;
+    float *part = a.partial32 + ((int64_t)s * multi_rows(lmax) + multi_row_start(lmax, m)) * NC;
+    // partial offset (within a tile) of the o-th value this lane adds: value v = half*NOWN + o
+    auto own_offset = [&](int o) {
+        const int v = half * NOWN + o, n = v >> 2, r = v & 3;
+        return (drow + 2 * r) * NC + (nt0 + n) * 16 + frow;
+    };
 
     for (int64_t g = g_a; g < g_b; ++g) {
         const bool first = (g == g_a);
-        // ---- 1. point data and this point's row of B ------------------------
+        // ---- 1. point data; stage B = w Z (FP32) and x --------------------------
         const int64_t i = g * kG + tid;
         double th = 1.5707963267948966, ph = 0.0;
         const bool valid = i < a.n;
@@ -135,28 +174,40 @@ __global__ __launch_bounds__(256) void alm_multi_kernel(MultiArgs a) {
                 renorm(br, bi, be);
             }
         }
-#pragma unroll 4
+        const float zr32 = (float)zr, zi32 = (float)zi;
+#pragma unroll 8
         for (int v = 0; v < NW; ++v) {
-            const double wv = valid ? (double)a.w32[(int64_t)v * a.n + i] : 0.0;
-            bf16_bits h, l;
-            split_bf16((float)(wv * zr), h, l);
-            Bh[(2 * v) * kRow + tid] = h;
-            Bl[(2 * v) * kRow + tid] = l;
-            split_bf16((float)(wv * zi), h, l);
-            Bh[(2 * v + 1) * kRow + tid] = h;
-            Bl[(2 * v + 1) * kRow + tid] = l;
+            const float wv = valid ? a.w32[(int64_t)v * a.n + i] : 0.f;
+            Bs[(2 * v) * kRowB + tid] = wv * zr32;
+            Bs[(2 * v + 1) * kRowB + tid] = wv * zi32;
         }
+        Xs[tid] = (float)x;
         __syncthreads();
-        // B fragments of this wavefront, kept for every l-tile of this group
-        bf16x8 bh[NTW][kG / 32], bl[NTW][kG / 32];
+        // B fragments of this wavefront's points (x folded in for the odd-l
+        // rows), kept for every l-tile of this group
+        bf16x8 bh[NTW][KS], bl[NTW][KS];
 #pragma unroll
         for (int n = 0; n < NTW; ++n)
 #pragma unroll
-            for (int ks = 0; ks < kG / 32; ++ks) {
-                const int off = ((nt0 + n) * 16 + frow) * kRow + ks * 32 + fk;
-                bh[n][ks] = load_frag(Bh + off);
-                bl[n][ks] = load_frag(Bl + off);
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k0 = kbase + ks * 32 + fk;
+                const float *bp = Bs + ((nt0 + n) * 16 + frow) * kRowB + k0;
+                const f32x4 b0 = *reinterpret_cast<const f32x4 *>(bp);
+                const f32x4 b1 = *reinterpret_cast<const f32x4 *>(bp + 4);
+                f32x4 x0 = *reinterpret_cast<const f32x4 *>(Xs + k0);
+                f32x4 x1 = *reinterpret_cast<const f32x4 *>(Xs + k0 + 4);
+                if (mt == 0) x0 = x1 = (f32x4){1.f, 1.f, 1.f, 1.f};
+                const float f[8] = {b0[0] * x0[0], b0[1] * x0[1], b0[2] * x0[2], b0[3] * x0[3],
+                                    b1[0] * x1[0], b1[1] * x1[1], b1[2] * x1[2], b1[3] * x1[3]};
+                uint4 h, l;
+                split_pair(f[0], f[1], h.x, l.x);
+                split_pair(f[2], f[3], h.y, l.y);
+                split_pair(f[4], f[5], h.z, l.z);
+                split_pair(f[6], f[7], h.w, l.w);
+                bh[n][ks] = __builtin_bit_cast(bf16x8, h);
+                bl[n][ks] = __builtin_bit_cast(bf16x8, l);
             }
+        __syncthreads();   // the staging region becomes the A tiles
 
         // ---- 2. l-tiles, software pipelined: the MFMAs of tile t read one A
         // buffer while the recurrence writes tile t+1 into the other ----------
@@ -165,100 +216,117 @@ __global__ __launch_bounds__(256) void alm_multi_kernel(MultiArgs a) {
         // s^m = 0 for m > 0 and contributes nothing (its chain is not bounded by
         // a physical value there, so it must not reach A)
         int q = (zr == 0.0 && zi == 0.0) ? -100000 : ze;
-        // A values of 32 steps starting at jb into buffer b (entries past lmax-m
-        // read the zero padding of the coefficient table and are never flushed)
-        auto recur_tile = [&](int jb, int b) {
-#pragma unroll
-            for (int k = 0; k < kLT; ++k) {
-                const double c = cm[jb + k];
-                double val;
-                if ((k & 1) == 0) {
-                    E = fma(c * y, O, -E);
-                    val = E;
-                } else {
-                    O = fma(c, E, -O);
-                    val = O * x;
-                }
-                bf16_bits h, l;
-                split_bf16((float)ldexp_d(val, q), h, l);
-                Ah[b][k * kRow + tid] = h;
-                Al[b][k * kRow + tid] = l;
-            }
+        // one recurrence pair (steps k, k+1 with coefficients c0, c1): its two A
+        // values, split, into rows k/2 (even l) and 16 + k/2 (odd l) of buffer b
+        auto recur_pair = [&](double c0, double c1, int k, int b) {
+            bf16_bits *ah = At + (2 * b) * kATile + tid;
+            bf16_bits *al = ah + kATile;
+            E = fma(c0 * y, O, -E);
+            O = fma(c1, E, -O);
+            unsigned hi, lo;
+            split_pair(opaque((float)ldexp_d(E, q)), opaque((float)ldexp_d(O, q)), hi, lo);
+            ah[(k >> 1) * kRowA] = (bf16_bits)hi;
+            ah[(kLT / 2 + (k >> 1)) * kRowA] = (bf16_bits)(hi >> 16);
+            al[(k >> 1) * kRowA] = (bf16_bits)lo;
+            al[(kLT / 2 + (k >> 1)) * kRowA] = (bf16_bits)(lo >> 16);
         };
-        recur_tile(0, 0);
+#pragma unroll
+        for (int k = 0; k < kLT; k += 2) recur_pair(cm[k], cm[k + 1], k, 0);
         __syncthreads();
         const int ntiles = (L + kLT - 1) / kLT;
+        constexpr int kUnits = NTW * KS;   // (K-step, N-tile) units of 3 MFMAs per tile
         for (int t = 0; t < ntiles; ++t) {
             const int jb = t * kLT;
             const int b = t & 1;
-            // previous partials of this tile, fetched before the work that hides their latency
-            float prev[NTW][4];
+            float *pt = part + (int64_t)jb * NC;
+            // previous partials of the values this lane adds, fetched before the
+            // work that hides their latency
+            float prev[NOWN];
 #pragma unroll
-            for (int n = 0; n < NTW; ++n) {
-                const int col = (nt0 + n) * 16 + frow;
-                const float *pc = part + (int64_t)(col >> 1) * 2 * T + (col & 1);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = jb + mt * 16 + 4 * (lane >> 4) + r;
-                    prev[n][r] = (!first && j < L) ? pc[2 * (col0 + j)] : 0.f;
-                }
+            for (int o = 0; o < NOWN; ++o) {
+                const float v = pt[own_offset(o)];
+                prev[o] = first ? 0.f : v;
             }
+            // step coefficients of the next tile (the tile after the last reads
+            // the table's padding; steps past lmax-m land in padding rows)
+            double cf[kLT];
+#pragma unroll
+            for (int k = 0; k < kLT; ++k) cf[k] = cm[jb + kLT + k];
             f32x4 d[NTW];
 #pragma unroll
             for (int n = 0; n < NTW; ++n) d[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const bf16_bits *ah = At + (2 * b) * kATile + (mt * 16 + frow) * kRowA + kbase + fk;
+            bf16x8 fa_h[KS], fa_l[KS];
+            fa_h[0] = load_frag(ah);
+            fa_l[0] = load_frag(ah + kATile);
+            // The MFMAs of this tile interleaved with the recurrence of the next
+            // one, in issue order fixed by scheduling fences, so one wavefront
+            // keeps the matrix core and the vector ALU busy at the same time; each
+            // K-step's A fragments are read one K-step ahead.
 #pragma unroll
-            for (int ks = 0; ks < kG / 32; ++ks) {
-                const int off = (mt * 16 + frow) * kRow + ks * 32 + fk;
-                const bf16x8 ah = load_frag(Ah[b] + off);
-                const bf16x8 al = load_frag(Al[b] + off);
+            for (int i = 0; i < kLT / 2; ++i) {
 #pragma unroll
-                for (int n = 0; n < NTW; ++n) {
-                    d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[n][ks], d[n], 0, 0, 0);
-                    d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[n][ks], d[n], 0, 0, 0);
-                    d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[n][ks], d[n], 0, 0, 0);
+                for (int u = i * kUnits / (kLT / 2); u < (i + 1) * kUnits / (kLT / 2); ++u) {
+                    const int ks = u / NTW, n = u % NTW;
+                    if (n == 0 && ks + 1 < KS) {
+                        fa_h[ks + 1] = load_frag(ah + (ks + 1) * 32);
+                        fa_l[ks + 1] = load_frag(ah + kATile + (ks + 1) * 32);
+                    }
+                    d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_h[ks], bh[n][ks], d[n], 0, 0, 0);
+                    d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_h[ks], bl[n][ks], d[n], 0, 0, 0);
+                    d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_l[ks], bh[n][ks], d[n], 0, 0, 0);
                 }
-            }
-            recur_tile(jb + kLT, b ^ 1);
-            // D[row][col]: row = 4*(lane/16) + r, col = lane % 16 (checked layout)
-#pragma unroll
-            for (int n = 0; n < NTW; ++n) {
-                const int col = (nt0 + n) * 16 + frow;
-                float *pc = part + (int64_t)(col >> 1) * 2 * T + (col & 1);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = jb + mt * 16 + 4 * (lane >> 4) + r;
-                    if (j < L) pc[2 * (col0 + j)] = prev[n][r] + d[n][r];
-                }
+                recur_pair(cf[2 * i], cf[2 * i + 1], 2 * i, b ^ 1);
+                __builtin_amdgcn_sched_barrier(0);
             }
             // keep the chain inside the FP64 range (growth < 2^255 per 64 steps)
-            if ((t & 1) == 1) {
+            {
                 const double mx = fmax(fabs(E), fabs(O));
-                if (mx > kChainAbove) {
-                    const int e = frexp_exp_d(mx);
-                    E = ldexp_d(E, -e);
-                    O = ldexp_d(O, -e);
-                    q += e;
-                }
+                const int e = mx > kChainAbove ? frexp_exp_d(mx) : 0;
+                E = ldexp_d(E, -e);
+                O = ldexp_d(O, -e);
+                q += e;
             }
+            // D[row][col]: row = 4*(lane/16) + r, col = lane % 16 (checked layout);
+            // value v = 4 n + r.  Hand the values the partner adds to it.
+            float dv[NV];
+#pragma unroll
+            for (int n = 0; n < NTW; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dv[4 * n + r] = d[n][r];
+            float *xw = xch + ((b * (kG / 64) + wave) * NOWN) * 64 + lane;
+            const float *xr = xch + ((b * (kG / 64) + partner) * NOWN) * 64 + lane;
+#pragma unroll
+            for (int o = 0; o < NOWN; ++o) xw[o * 64] = half ? dv[o] : dv[NOWN + o];
             __syncthreads();
+#pragma unroll
+            for (int o = 0; o < NOWN; ++o) {
+                const float mine = half ? dv[NOWN + o] : dv[o];
+                pt[own_offset(o)] = prev[o] + (mine + xr[o * 64]);
+            }
         }
     }
 }
 
-// out[v][k] = sigma_k * sum_s partial[s][v][k] (FP64 sum in slice order)
+// out[v][column_start(m) + j] = sigma * sum_s partial[s][row(m) + j][2v, 2v+1]
+// (FP64 sum in slice order); one workgroup per order m
 __global__ void multi_finish_kernel(const float *__restrict__ partial, int n_slices, int nw,
-                                    const double *__restrict__ sigma, int64_t T, double *__restrict__ alm) {
-    const int64_t total = (int64_t)nw * T;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = e % T;
+                                    const double *__restrict__ sigma, int lmax, double *__restrict__ alm) {
+    const int m = blockIdx.x;
+    const int L = lmax - m + 1;
+    const int64_t T = tri_size(lmax), rows = multi_rows(lmax);
+    const int64_t c0 = column_start(lmax, m), r0 = multi_row_start(lmax, m);
+    const int nc = 2 * nw;
+    for (int e = threadIdx.x; e < L * nw; e += blockDim.x) {
+        const int v = e / L, j = e - v * L;
         double re = 0.0, im = 0.0;
         for (int s = 0; s < n_slices; ++s) {
-            const float2 v = reinterpret_cast<const float2 *>(partial + (int64_t)s * nw * 2 * T)[e];
-            re += (double)v.x;
-            im += (double)v.y;
+            const float2 p = *reinterpret_cast<const float2 *>(partial + ((int64_t)s * rows + r0 + j) * nc + 2 * v);
+            re += (double)p.x;
+            im += (double)p.y;
         }
-        const double sg = sigma[k];
-        reinterpret_cast<double2 *>(alm)[e] = make_double2(sg * re, sg * im);
+        const double sg = sigma[c0 + j];
+        reinterpret_cast<double2 *>(alm)[(int64_t)v * T + c0 + j] = make_double2(sg * re, sg * im);
     }
 }
 
@@ -284,16 +352,15 @@ hipError_t launch_alm_multi(const MultiArgs &a, hipStream_t stream) {
     if (e != hipSuccess) return e;
     const int blocks = (a.lmax + 1) * a.n_slices;
     if (a.n_weights == 32)
-        hipLaunchKernelGGL(alm_multi_kernel<32>, dim3(blocks), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(alm_multi_kernel<32>, dim3(blocks), dim3(kG), 0, stream, a);
     else
-        hipLaunchKernelGGL(alm_multi_kernel<16>, dim3(blocks), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(alm_multi_kernel<16>, dim3(blocks), dim3(kG), 0, stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_multi_finish(const MultiArgs &a, const double *sigma, double *alm, hipStream_t stream) {
-    const int64_t T = tri_size(a.lmax);
-    hipLaunchKernelGGL(multi_finish_kernel, dim3(grid_for((int64_t)a.n_weights * T, 256)), dim3(256), 0, stream,
-                       a.partial32, a.n_slices, a.n_weights, sigma, T, alm);
+    hipLaunchKernelGGL(multi_finish_kernel, dim3(a.lmax + 1), dim3(256), 0, stream,
+                       a.partial32, a.n_slices, a.n_weights, sigma, a.lmax, alm);
     return hipGetLastError();
 }
 

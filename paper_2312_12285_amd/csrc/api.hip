@@ -137,6 +137,7 @@ constexpr int kMixedKP = 8;   // 238 VGPRs: two wavefronts per SIMD
 constexpr int kFp32KP = 10;
 constexpr int kTargetItems = 8192;   // (slice, range) items: ~4 per resident wavefront
 constexpr int kMaxSlices = 32;
+constexpr int64_t kMaxItems = int64_t(1) << 22;   // workgroups of one launch (x 512 threads < 2^32)
 
 struct Resolved {
     int precision, n_weights, kp, lb, mode, S, R;
@@ -152,25 +153,25 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     if (o->precision != PTALM_FP64 && o->precision != PTALM_MIXED && o->precision != PTALM_FP32 &&
         o->precision != PTALM_BF16X3)
         return fail(PTALM_EINVAL, "bad precision");
+    if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0 ||
+        o->reduction < 0 || o->reduction > 4)
+        return fail(PTALM_EINVAL, "option out of range");
+    if (o->n_slices > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
     if (o->precision == PTALM_BF16X3) {
         if (!ptalm::multi_nw_supported(r->n_weights))
             return fail(PTALM_ENOTSUP, "the split-bf16 MFMA form needs n_weights 16 or 32");
         r->kp = 0;
         r->lb = 0;
         r->mode = 0;
-        r->groups = (n + 255) / 256;
+        r->groups = (n + ptalm::kMultiGroup - 1) / ptalm::kMultiGroup;
         const int64_t want = (512 + lmax) / (lmax + 1);
         int64_t S = o->n_slices ? o->n_slices : want;
         if (S > std::max<int64_t>(1, r->groups)) S = std::max<int64_t>(1, r->groups);
-        if (S > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
+        if (S * (lmax + 1) > kMaxItems) return fail(PTALM_EINVAL, "n_slices x (lmax+1) work items exceed 2^22");
         r->S = (int)S;
         r->R = lmax + 1;
         return PTALM_OK;
     }
-    if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0 ||
-        o->reduction < 0 || o->reduction > 4)
-        return fail(PTALM_EINVAL, "option out of range");
-    if (o->n_slices > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
     const int def_kp = r->precision == PTALM_FP64 ? kDefaultKP : (r->precision == PTALM_MIXED ? kMixedKP : kFp32KP);
     r->kp = o->points_per_lane ? o->points_per_lane : def_kp;
     r->lb = o->l_block ? o->l_block : kDefaultLB;
@@ -185,6 +186,7 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     r->S = (int)S;
     int R = o->m_ranges ? o->m_ranges : (int)std::max<int64_t>(1, kTargetItems / S);
     if (R > lmax + 1) R = lmax + 1;
+    if ((int64_t)S * R > kMaxItems) return fail(PTALM_EINVAL, "n_slices x m_ranges work items exceed 2^22");
     r->R = R;
     return PTALM_OK;
 }
@@ -195,9 +197,9 @@ size_t partial_bytes(const Resolved &r, int lmax) {
     return sizeof(double) * 2 * (size_t)ptalm::tri_size(lmax) * (size_t)r.S;
 }
 
-// multi-weight MFMA scratch: FP32 partials [S][NW][2T], then the FP32 weight copy
+// multi-weight MFMA scratch: FP32 partials [S][rows][2 NW], then the FP32 weight copy
 size_t multi_partial_bytes(const Resolved &r, int lmax) {
-    return align256(sizeof(float) * 2 * (size_t)ptalm::tri_size(lmax) * (size_t)r.n_weights * (size_t)r.S);
+    return align256(sizeof(float) * 2 * (size_t)ptalm::multi_rows(lmax) * (size_t)r.n_weights * (size_t)r.S);
 }
 size_t multi_bytes(const Resolved &r, int64_t n, int lmax) {
     return multi_partial_bytes(r, lmax) + align256(sizeof(float) * (size_t)n * (size_t)r.n_weights);
@@ -247,6 +249,7 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
     if (rc) return rc;
     const size_t need = r.precision == PTALM_BF16X3 ? multi_bytes(r, n, lmax) : partial_bytes(r, lmax);
     if (workspace != nullptr && ws_bytes < need) return fail(PTALM_EINVAL, "workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(PTALM_EINVAL, "workspace not 256-byte aligned");
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t T = ptalm::tri_size(lmax);
     hipError_t e;

@@ -78,10 +78,22 @@ struct MultiArgs {
     int lmax;
     int n_weights;            // 16 or 32
     int n_slices;
-    int64_t groups;           // ceil(n / 256)
+    int64_t groups;           // ceil(n / kMultiGroup)
     const double *coef;       // device step coefficients
-    float *partial32;         // device, n_slices * n_weights * 2T floats
+    float *partial32;         // device, [n_slices][multi_rows(lmax)][2 n_weights] floats
 };
+
+// Rows of the multi-weight partial buffer: order m's segment starts at
+// column_start(m) + kMultiPad*m and holds L(m) rows plus kMultiPad rows of
+// padding, so whole 32-row tiles can be read and written without bounds tests.
+constexpr int kMultiPad = 32;
+constexpr int kMultiGroup = 512;   // points per group = threads per workgroup
+__host__ __device__ inline int64_t multi_row_start(int lmax, int m) {
+    return column_start(lmax, m) + (int64_t)m * kMultiPad;
+}
+__host__ __device__ inline int64_t multi_rows(int lmax) {
+    return tri_size(lmax) + (int64_t)(lmax + 1) * kMultiPad;
+}
 
 // --- launchers (defined in the .hip files) ----------------------------------
 hipError_t build_tables(int lmax, Tables *t, hipStream_t stream);

@@ -87,3 +87,44 @@ def test_workspace_bytes_matches_plan(lib):
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0
     o = Opts(5, 1, 0, 0, 0, 0, 0, 0)    # bad precision
     assert lib.ptalm_workspace_bytes(100, 64, ctypes.byref(o)) == 0
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int) for f in ("precision", "n_weights", "points_per_lane", "l_block",
+                                              "n_slices", "m_ranges", "reduction", "timing")]
+
+
+def _ws(lib, n, lmax, o):
+    lib.ptalm_workspace_bytes.restype = ctypes.c_size_t
+    lib.ptalm_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_Opts)]
+    return lib.ptalm_workspace_bytes(n, lmax, ctypes.byref(o))
+
+
+def test_multi_weight_workspace_bytes(lib):
+    def a256(b):
+        return (b + 255) // 256 * 256
+    for n, lmax, nw, S in [(10 ** 6, 2048, 32, 0), (1000, 64, 16, 0), (1000, 64, 16, 3)]:
+        o = _Opts(3, nw, 0, 0, S, 0, 0, 0)
+        groups = (n + 511) // 512                                     # 512 points per group
+        s = min(S if S else (512 + lmax) // (lmax + 1), max(1, groups))   # clamped to the groups
+        rows = (lmax + 1) * (lmax + 2) // 2 + 32 * (lmax + 1)     # every order padded by one 32-row tile
+        assert _ws(lib, n, lmax, o) == a256(4 * 2 * nw * rows * s) + a256(4 * n * nw)
+    assert _ws(lib, 1000, 64, _Opts(3, 8, 0, 0, 0, 0, 0, 0)) == 0        # unsupported weight count
+    assert _ws(lib, 1000, 64, _Opts(3, 16, 0, 0, -1, 0, 0, 0)) == 0      # negative option
+
+
+def test_extended_call_rejects_bad_workspace_and_sizes(lib):
+    """Argument checks that return before any device call (fake device pointers)."""
+    f = lib.ptalm_alm_from_points_ex
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                  ctypes.POINTER(_Opts), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    fake = 1 << 40
+    o = _Opts(3, 16, 0, 0, 0, 0, 0, 0)
+    need = _ws(lib, 1000, 64, o)
+    assert f(fake, fake, fake, 1000, 64, fake, ctypes.byref(o), fake + 8, need, None) == -1       # misaligned
+    assert f(fake, fake, fake, 1000, 64, fake, ctypes.byref(o), fake, need - 1, None) == -1       # too small
+    big = _Opts(0, 1, 6, 16, 65536, 16384, 0, 0)                                             # 2^30 work items
+    assert f(fake, fake, fake, 10 ** 9, 16383, fake, ctypes.byref(big), None, 0, None) == -1
+    big = _Opts(3, 16, 0, 0, 512, 0, 0, 0)                                                  # 512 x 16384 items
+    assert f(fake, fake, fake, 10 ** 9, 16383, fake, ctypes.byref(big), None, 0, None) == -1
