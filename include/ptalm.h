@@ -42,7 +42,7 @@ typedef enum {
     PTALM_EINVAL = -1,   /* bad argument; nothing enqueued, outputs untouched   */
     PTALM_ENOMEM = -2,   /* device allocation of scratch or tables failed        */
     PTALM_EDEVICE = -3,  /* HIP runtime error                                    */
-    PTALM_EBUSY = -4,    /* server: request does not fit the memory budget now  */
+    PTALM_EBUSY = -4,    /* not now: server budget full, or tables not prepared under capture */
     PTALM_ENOTSUP = -5   /* option combination not implemented                   */
 } ptalm_status;
 
@@ -160,10 +160,29 @@ int ptalm_last_timing(double *transform_ms);
  * that one-off cost out of a timed region or a latency-sensitive loop. */
 int ptalm_prepare(int lmax);
 
+/* Builds everything the call ptalm_alm_from_points_ex(n, lmax, opts, ...)
+ * would build on first use (coefficient tables, m-range table), so that the
+ * call can afterwards be captured into a HIP graph: under stream capture the
+ * transform allocates and synchronizes nothing, needs a caller workspace and
+ * returns PTALM_EBUSY if the tables were not prepared.  Host only. */
+int ptalm_prepare_call(int64_t n, int lmax, const ptalm_opts *opts);
+
+/* Autotuner.  Times, on `stream` with HIP events, one call of every compiled
+ * kernel variant of `precision` (points per lane x l-block x reduction for the
+ * vector forms; point slices for PTALM_BF16X3) on the given points (device
+ * pointers as in ptalm_alm_from_points_ex; a few 1e5 points are a good
+ * sample), and writes the fastest options to *best.  The choice is also kept
+ * per (device, precision, n_weights, lmax) and used for every option left at
+ * 0 in later calls.  Synchronizes `stream`; allocates and frees stream-ordered
+ * scratch.  PTALM_EINVAL on bad arguments or under stream capture. */
+int ptalm_autotune(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
+                   int precision, int n_weights, ptalm_opts *best, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). Host only. */
 const char *ptalm_last_error(void);
 
-/* Frees the per-device tables cached by earlier calls (coefficients per lmax).
+/* Frees the per-device tables cached by earlier calls (coefficients per lmax)
+ * and forgets the autotuner's choices.
  * Call only when no work of this library is pending on the current device. */
 int ptalm_release_cache(void);
 

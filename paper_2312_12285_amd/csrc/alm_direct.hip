@@ -400,6 +400,22 @@ hipError_t launch_one(const AlmArgs &a, hipStream_t stream) {
 
 #define PTALM_MATCH(K, L, S, P) (kp == K && lb == L && mode == (S | (P << 1)))
 
+int list_variants(int precision, int (*out)[3], int max) {
+    int k = 0;
+#define X(K, L, S, P)               \
+    if (k < max) {                  \
+        out[k][0] = K;              \
+        out[k][1] = L;              \
+        out[k][2] = S | (P << 1);   \
+    }                               \
+    ++k;
+    if (precision == 0) { PTALM_FP64_VARIANTS(X) }
+    else if (precision == 1) { PTALM_MIXED_VARIANTS(X) }
+    else if (precision == 2) { PTALM_FP32_VARIANTS(X) }
+#undef X
+    return k;
+}
+
 bool fp64_variant_exists(int kp, int lb, int mode) {
 #define X(K, L, S, P) if (PTALM_MATCH(K, L, S, P)) return true;
     PTALM_FP64_VARIANTS(X)

@@ -44,12 +44,19 @@ std::mutex g_mu;
 std::map<std::pair<int, int>, ptalm::Tables> g_tables;          // (device, lmax)
 std::map<std::tuple<int, int, int>, int *> g_ranges;            // (device, lmax, R)
 
+// Kernel choices found by ptalm_autotune, per (device, precision, n_weights,
+// lmax); used for every option left at 0 in later calls.
+struct Tuned {
+    int kp = 0, lb = 0, mode = 0, slices = 0;
+};
+std::map<std::tuple<int, int, int, int>, Tuned> g_tuned;
+
 int current_device(int *dev) {
     hipError_t e = hipGetDevice(dev);
     return e == hipSuccess ? PTALM_OK : fail_hip(e, "hipGetDevice");
 }
 
-int get_tables(int lmax, const ptalm::Tables **out) {
+int get_tables(int lmax, const ptalm::Tables **out, bool may_build = true) {
     int dev;
     int rc = current_device(&dev);
     if (rc) return rc;
@@ -59,6 +66,7 @@ int get_tables(int lmax, const ptalm::Tables **out) {
         *out = &it->second;
         return PTALM_OK;
     }
+    if (!may_build) return fail(PTALM_EBUSY, "coefficient tables not prepared (call ptalm_prepare_call before capture)");
     ptalm::Tables t;
     hipStream_t s;
     hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
@@ -103,7 +111,7 @@ extern "C" int ptalm_plan_m_ranges(int lmax, int R, int *bounds) {
 
 namespace {
 
-int get_ranges(int lmax, int R, const int **out) {
+int get_ranges(int lmax, int R, const int **out, bool may_build = true) {
     int dev;
     int rc = current_device(&dev);
     if (rc) return rc;
@@ -114,6 +122,7 @@ int get_ranges(int lmax, int R, const int **out) {
         *out = it->second;
         return PTALM_OK;
     }
+    if (!may_build) return fail(PTALM_EBUSY, "m-range table not prepared (call ptalm_prepare_call before capture)");
     std::vector<int> b(R + 1);
     ptalm_plan_m_ranges(lmax, R, b.data());
     int *d = nullptr;
@@ -144,6 +153,22 @@ struct Resolved {
     int64_t groups;
 };
 
+// Tuned entry for the current device, if ptalm_autotune stored one (no device
+// query while the table is empty, so host-only callers never touch HIP).
+bool tuned_lookup(int precision, int nw, int lmax, Tuned *t) {
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        if (g_tuned.empty()) return false;
+    }
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_tuned.find(std::make_tuple(dev, precision, nw, lmax));
+    if (it == g_tuned.end()) return false;
+    *t = it->second;
+    return true;
+}
+
 int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     ptalm_opts d;
     memset(&d, 0, sizeof d);
@@ -164,7 +189,9 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
         r->lb = 0;
         r->mode = 0;
         r->groups = (n + ptalm::kMultiGroup - 1) / ptalm::kMultiGroup;
-        const int64_t want = (512 + lmax) / (lmax + 1);
+        Tuned tu;
+        const bool tuned = o->n_slices == 0 && tuned_lookup(PTALM_BF16X3, r->n_weights, lmax, &tu);
+        const int64_t want = tuned ? tu.slices : (512 + lmax) / (lmax + 1);
         int64_t S = o->n_slices ? o->n_slices : want;
         if (S > std::max<int64_t>(1, r->groups)) S = std::max<int64_t>(1, r->groups);
         if (S * (lmax + 1) > kMaxItems) return fail(PTALM_EINVAL, "n_slices x (lmax+1) work items exceed 2^22");
@@ -172,10 +199,18 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
         r->R = lmax + 1;
         return PTALM_OK;
     }
-    const int def_kp = r->precision == PTALM_FP64 ? kDefaultKP : (r->precision == PTALM_MIXED ? kMixedKP : kFp32KP);
+    int def_kp = r->precision == PTALM_FP64 ? kDefaultKP : (r->precision == PTALM_MIXED ? kMixedKP : kFp32KP);
+    int def_lb = kDefaultLB, def_mode = kDefaultMode;
+    Tuned tu;
+    if ((o->points_per_lane == 0 || o->l_block == 0 || o->reduction == 0) &&
+        tuned_lookup(r->precision, r->n_weights, lmax, &tu)) {
+        def_kp = tu.kp;
+        def_lb = tu.lb;
+        def_mode = tu.mode;
+    }
     r->kp = o->points_per_lane ? o->points_per_lane : def_kp;
-    r->lb = o->l_block ? o->l_block : kDefaultLB;
-    r->mode = o->reduction ? o->reduction - 1 : kDefaultMode;
+    r->lb = o->l_block ? o->l_block : def_lb;
+    r->mode = o->reduction ? o->reduction - 1 : def_mode;
     const bool have = r->precision == PTALM_FP64    ? ptalm::fp64_variant_exists(r->kp, r->lb, r->mode)
                       : r->precision == PTALM_MIXED ? ptalm::mixed_variant_exists(r->kp, r->lb, r->mode)
                                                     : ptalm::fp32_variant_exists(r->kp, r->lb, r->mode);
@@ -252,17 +287,24 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
     if (((uintptr_t)workspace & 255) != 0) return fail(PTALM_EINVAL, "workspace not 256-byte aligned");
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t T = ptalm::tri_size(lmax);
-    hipError_t e;
+    const bool timed = opts != nullptr && opts->timing != 0;
+    // Under stream capture nothing may allocate or synchronize: the tables must
+    // exist already and the caller must bring the workspace.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cap);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing && timed) return fail(PTALM_EINVAL, "timing is not available under stream capture");
+    if (capturing && n > 0 && workspace == nullptr) return fail(PTALM_EINVAL, "stream capture needs a caller workspace");
     if (n == 0) {
-        e = hipMemsetAsync(alm, 0, sizeof(double) * 2 * T * r.n_weights, stream);
-        return e == hipSuccess ? PTALM_OK : fail_hip(e, "hipMemsetAsync");
+        e = ptalm::launch_zero(alm, 2 * T * r.n_weights, stream);
+        return e == hipSuccess ? PTALM_OK : fail_hip(e, "zero kernel launch");
     }
     const ptalm::Tables *tab;
-    if ((rc = get_tables(lmax, &tab))) return rc;
-    const int *ranges;
-    if ((rc = get_ranges(lmax, r.R, &ranges))) return rc;
+    if ((rc = get_tables(lmax, &tab, !capturing))) return rc;
+    const int *ranges = nullptr;
+    if (r.precision != PTALM_BF16X3 && (rc = get_ranges(lmax, r.R, &ranges, !capturing))) return rc;
 
-    const bool timed = opts != nullptr && opts->timing != 0;
     if (timed) {
         g_timing.valid = false;
         if (!g_timing.start && (e = hipEventCreate(&g_timing.start)) != hipSuccess) return fail_hip(e, "hipEventCreate");
@@ -393,6 +435,122 @@ int ptalm_prepare(int lmax) {
     return get_tables(lmax, &tab);
 }
 
+int ptalm_prepare_call(int64_t n, int lmax, const ptalm_opts *opts) {
+    g_error.clear();
+    if (n < 0) return fail(PTALM_EINVAL, "n < 0");
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    Resolved r;
+    int rc = resolve(n, lmax, opts, &r);
+    if (rc) return rc;
+    const ptalm::Tables *tab;
+    if ((rc = get_tables(lmax, &tab))) return rc;
+    const int *ranges;
+    if (r.precision != PTALM_BF16X3 && (rc = get_ranges(lmax, r.R, &ranges))) return rc;
+    return PTALM_OK;
+}
+
+int ptalm_autotune(const double *theta, const double *phi, const double *w, int64_t n, int lmax, int precision,
+                   int n_weights, ptalm_opts *best, void *stream_) {
+    g_error.clear();
+    if (n <= 0) return fail(PTALM_EINVAL, "autotune needs n > 0");
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (theta == nullptr || phi == nullptr || w == nullptr || best == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    if (precision < PTALM_FP64 || precision > PTALM_BF16X3) return fail(PTALM_EINVAL, "bad precision");
+    if (n_weights < 1) return fail(PTALM_EINVAL, "n_weights < 1");
+    hipStream_t stream = (hipStream_t)stream_;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cap);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone) return fail(PTALM_EINVAL, "autotune cannot run under stream capture");
+
+    // candidates: every compiled kernel variant (VALU forms) or slice count (MFMA form)
+    std::vector<ptalm_opts> cands;
+    std::vector<int> seen_slices;
+    auto base = [&]() {
+        ptalm_opts o;
+        memset(&o, 0, sizeof o);
+        o.precision = precision;
+        o.n_weights = n_weights;
+        return o;
+    };
+    if (precision == PTALM_BF16X3) {
+        for (int S : {1, 2, 4, 8}) {
+            ptalm_opts o = base();
+            o.n_slices = S;
+            Resolved r;
+            int rc = resolve(n, lmax, &o, &r);
+            if (rc) return rc;
+            if (std::find(seen_slices.begin(), seen_slices.end(), r.S) != seen_slices.end()) continue;
+            seen_slices.push_back(r.S);
+            o.n_slices = r.S;
+            cands.push_back(o);
+        }
+    } else {
+        int v[64][3];
+        const int k = std::min(64, ptalm::list_variants(precision, v, 64));
+        for (int i = 0; i < k; ++i) {
+            ptalm_opts o = base();
+            o.points_per_lane = v[i][0];
+            o.l_block = v[i][1];
+            o.reduction = v[i][2] + 1;
+            cands.push_back(o);
+        }
+    }
+    size_t ws = 0;
+    for (const ptalm_opts &o : cands) {
+        Resolved r;
+        int rc = resolve(n, lmax, &o, &r);
+        if (rc) return rc;
+        ws = std::max(ws, r.precision == PTALM_BF16X3 ? multi_bytes(r, n, lmax) : partial_bytes(r, lmax));
+    }
+    const size_t out_bytes = sizeof(double) * 2 * (size_t)ptalm::tri_size(lmax) * (size_t)n_weights;
+    void *buf = nullptr;
+    if ((e = hipMallocAsync(&buf, align256(out_bytes) + ws, stream)) != hipSuccess) return fail_hip(e, "hipMallocAsync");
+    double *out = (double *)buf;
+    void *wsp = (char *)buf + align256(out_bytes);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = PTALM_OK;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) rc = fail_hip(e, "hipEventCreate");
+    float best_ms = -1.f;
+    ptalm_opts pick = cands.empty() ? base() : cands[0];
+    for (size_t c = 0; c < cands.size() && rc == PTALM_OK; ++c) {
+        // one untimed call (first touch of code and tables), then one timed call
+        rc = ptalm_alm_from_points_ex(theta, phi, w, n, lmax, out, &cands[c], wsp, ws, stream);
+        if (rc) break;
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) { rc = fail_hip(e, "hipEventRecord"); break; }
+        rc = ptalm_alm_from_points_ex(theta, phi, w, n, lmax, out, &cands[c], wsp, ws, stream);
+        if (rc) break;
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+            rc = fail_hip(e, "timing event");
+            break;
+        }
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = fail_hip(e, "hipEventElapsedTime"); break; }
+        if (best_ms < 0.f || ms < best_ms) {
+            best_ms = ms;
+            pick = cands[c];
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    e = hipFreeAsync(buf, stream);
+    if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync");
+    if (rc) return rc;
+    int dev;
+    if ((rc = current_device(&dev))) return rc;
+    Tuned t;
+    t.kp = pick.points_per_lane;
+    t.lb = pick.l_block;
+    t.mode = pick.reduction > 0 ? pick.reduction - 1 : 0;
+    t.slices = pick.n_slices;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_tuned[std::make_tuple(dev, precision, n_weights, lmax)] = t;
+    }
+    *best = pick;
+    return PTALM_OK;
+}
+
 int ptalm_release_cache(void) {
     std::lock_guard<std::mutex> lock(g_mu);
     for (auto &kv : g_tables) {
@@ -403,6 +561,7 @@ int ptalm_release_cache(void) {
     g_tables.clear();
     for (auto &kv : g_ranges) hipFree(kv.second);
     g_ranges.clear();
+    g_tuned.clear();
     return PTALM_OK;
 }
 

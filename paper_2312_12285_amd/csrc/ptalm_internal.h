@@ -104,12 +104,16 @@ hipError_t launch_reduce_partials(const double *partial, int n_slices, const dou
                                   double *alm, hipStream_t stream);
 hipError_t launch_cl(const double *alm1, const double *alm2, int lmax, double *cl, hipStream_t stream);
 hipError_t launch_axpy(double alpha, const double *x, double *y, int64_t count, hipStream_t stream);
+hipError_t launch_zero(double *p, int64_t count, hipStream_t stream);
 hipError_t launch_fkp(const double *ad, const double *ar, int lmax, double *delta, double *window,
                       double *alpha_out, hipStream_t stream);
 
 // Kernel variants compiled into the library, as (points_per_lane, l_block, mode)
 // with mode = register butterfly stage (bit 0) | pipelined reduction (bit 1).
 bool fp64_variant_exists(int kp, int lb, int mode);
+// (points_per_lane, l_block, mode) of every compiled variant of a precision
+// (0 FP64, 1 mixed, 2 FP32): writes min(count, max) entries, returns count
+int list_variants(int precision, int (*out)[3], int max);
 bool mixed_variant_exists(int kp, int lb, int mode);
 bool fp32_variant_exists(int kp, int lb, int mode);
 

@@ -27,6 +27,12 @@ __global__ __launch_bounds__(64) void cl_kernel(const double *__restrict__ a, co
     if (lane == 0) cl[l] = s / (2.0 * l + 1.0);
 }
 
+// p[0, count) = 0 (a kernel rather than a memset, so that a captured graph holds no memset node)
+__global__ void zero_kernel(double *__restrict__ p, int64_t count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0.0;
+}
+
 __global__ void axpy_kernel(double alpha, const double *__restrict__ x, double *__restrict__ y, int64_t count) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
         y[k] = fma(alpha, x[k], y[k]);
@@ -61,6 +67,11 @@ hipError_t launch_cl(const double *alm1, const double *alm2, int lmax, double *c
 
 hipError_t launch_axpy(double alpha, const double *x, double *y, int64_t count, hipStream_t stream) {
     hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(count, 256)), dim3(256), 0, stream, alpha, x, y, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, int64_t count, hipStream_t stream) {
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(count, 256)), dim3(256), 0, stream, p, count);
     return hipGetLastError();
 }
 

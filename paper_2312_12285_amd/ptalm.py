@@ -58,6 +58,9 @@ _last_timing = _sig("ptalm_last_timing", ctypes.c_int, [ctypes.POINTER(ctypes.c_
 _release = _sig("ptalm_release_cache", ctypes.c_int, [])
 _prepare = _sig("ptalm_prepare", ctypes.c_int, [ctypes.c_int])
 _plan_ranges = _sig("ptalm_plan_m_ranges", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
+_prepare_call = _sig("ptalm_prepare_call", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
+_autotune = _sig("ptalm_autotune", ctypes.c_int,
+                 [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts), _vp])
 
 
 class PtalmError(RuntimeError):
@@ -187,6 +190,27 @@ def fkp_fields(alm_data, alm_randoms, lmax: int, stream=None):
 def prepare(lmax: int):
     """Build the per-lmax coefficient tables on the current device ahead of first use."""
     _check(_prepare(lmax))
+
+
+def prepare_call(n: int, lmax: int, options: Opts | None = None):
+    """Build everything a later call with these arguments needs, so that it can be captured
+    into a HIP graph (under capture the library allocates nothing and needs a workspace)."""
+    o = options if options is not None else opts()
+    _check(_prepare_call(n, lmax, ctypes.byref(o)))
+
+
+def autotune(theta, phi, w, lmax: int, precision: int = FP64, stream=None) -> Opts:
+    """Time every compiled kernel variant of `precision` on these points and return the
+    fastest options; the library also keeps them as the defaults for (precision,
+    n_weights, lmax) on this device."""
+    _dev_f64(theta, "theta"); _dev_f64(phi, "phi"); _dev_f64(w, "w")
+    n = theta.numel()
+    nw = w.shape[0] if w.dim() == 2 else 1
+    if phi.numel() != n or w.numel() != nw * n:
+        raise ValueError("theta, phi and w rows must have the same length")
+    best = Opts()
+    _check(_autotune(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, precision, nw, ctypes.byref(best), _stream(stream)))
+    return best
 
 
 def release_cache():

@@ -39,7 +39,7 @@ def catalog(n, nw, seed=41):
 
 @pytest.mark.parametrize("nw", [16, 32])
 def test_bf16x3_small(lib, oracle, nw):
-    th, ph, W = catalog(2000 + 37, nw)          # 7 full groups of 256 and a ragged one
+    th, ph, W = catalog(2000 + 37, nw)          # 3 full groups of 512 points and a ragged one
     lmax = 100
     a = run(lib, th, ph, W, lmax, precision=lib.BF16X3)
     worst = 0.0
