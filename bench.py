@@ -12,6 +12,9 @@ Workloads (--workload):
   randoms3072  1e8 uniform-in-mask randoms, unit weights, lmax 3072   (default)
   galaxies1024 2e6 clustered galaxies (lognormal weights) + 2e7 randoms, lmax 1024
   fullsky64    1e4 uniform full-sky points, unit weights, lmax 64
+  multi2048    1e7 masked positions shared by 32 lognormal weight vectors, lmax 2048,
+               split-bf16 MFMA form; tuned by the library's autotuner on a prefix,
+               then each step replays one captured HIP graph (transform + 32 spectra)
 
 Besides value, the line carries the roofline of the transform kernel (its
 algorithmic FP64 work, 7 flops per term, over its device time measured with
@@ -30,6 +33,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 flop/clk/CU)
+BF16_PEAK_TFLOPS = 2500.0     # MI355X dense bf16 matrix peak
+MULTI_FLOPS_PER_TERM = 4      # per (point, l, m, weight vector): re and im multiply-adds
 FLOPS_PER_TERM = 7            # recurrence multiply + FMA, two accumulate FMAs
 METRIC = "point\u00b7(l,m) terms/s FP64 vs mixed at stated rel err; served p50/p99 latency"
 UNIT = "point\u00b7(l,m) terms/s"
@@ -39,6 +44,8 @@ WORKLOADS = {
     "galaxies1024": dict(desc="masked galaxies n=2e6 (2% jittered copies, lognormal sigma=0.3) + masked randoms "
                               "n=2e7, lmax=1024, C_l of galaxies - alpha randoms and W_l", lmax=1024),
     "fullsky64": dict(desc="full-sky uniform n=1e4, unit weights, lmax=64", lmax=64),
+    "multi2048": dict(desc="one masked position set n=1e7 shared by 32 lognormal weight vectors (sigma=0.2), "
+                           "lmax=2048, split-bf16 MFMA form", lmax=2048),
 }
 
 
@@ -80,6 +87,9 @@ def make_catalogs(name, scale):
                 ("randoms", synth.masked_randoms(int(2e7 * scale), seed=23))]
     if name == "fullsky64":
         return [("points", synth.fullsky_uniform(10_000, seed=1))]
+    if name == "multi2048":
+        t, p, W = synth.multi_weight_positions(int(1e7 * scale), 32, seed_pos=41, seed_w0=4100)
+        return [("positions", synth.Catalog(t, p, W))]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -126,6 +136,83 @@ def sampled_parity(cat, lmax, alm_dev):
             "oracle_seconds": round(dt, 1)}
 
 
+def run_multi(args, cats, lmax):
+    """multi2048: autotune on a prefix, capture transform + spectra once, replay per step."""
+    import numpy as np
+    import torch
+    from paper_2312_12285_amd import ptalm, synth
+    T = tri(lmax)
+    cat = cats[0][1]
+    n, nw = cat.n, cat.w.shape[0]
+    t = torch.as_tensor(cat.theta).cuda()
+    p = torch.as_tensor(cat.phi).cuda()
+    w = torch.as_tensor(cat.w).cuda()
+    k = min(n, 1_000_000)
+    print(f"[bench] autotune on the first {k} positions", file=sys.stderr, flush=True)
+    best = ptalm.autotune(t[:k].contiguous(), p[:k].contiguous(), w[:, :k].contiguous(), lmax, precision=ptalm.BF16X3)
+    torch.cuda.synchronize()
+    o = ptalm.opts(precision=ptalm.BF16X3, n_weights=nw)      # auto fields take the tuned choice
+    ptalm.prepare_call(n, lmax, o)
+    ws = torch.empty(ptalm.workspace_bytes(n, lmax, o), dtype=torch.uint8, device="cuda")
+    out = torch.empty((nw, 2 * T), dtype=torch.float64, device="cuda")
+    cls = torch.empty((nw, lmax + 1), dtype=torch.float64, device="cuda")
+
+    def body():
+        ptalm.alm_from_points(t, p, w, lmax, out=out, options=o, workspace=ws)
+        for v in range(nw):
+            ptalm.cl_from_alm(out[v], lmax, out=cls[v])
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        body()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    print("[bench] capturing one step into a HIP graph", file=sys.stderr, flush=True)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        body()
+    for i in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} graph replay(s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        g.replay()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    weight_terms = nw * n * T
+    value = weight_terms * args.steps / elapsed
+    useful = MULTI_FLOPS_PER_TERM * weight_terms
+    achieved = useful / (step_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "alm_multi_kernel<32>", "kernel_ms_per_launch": round(step_ms, 3),
+                "timed_span": "whole replayed graph (transform + 32 spectra), events on the replay stream",
+                "flops_per_weight_term": MULTI_FLOPS_PER_TERM, "issued_mfma_flops_per_useful": 3}
+    line = {"metric": METRIC, "value": value, "unit": UNIT + " (summed over the weight vectors)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16x3 split products, f32 accumulate, f64 recurrence", "data": "synthetic",
+            "config": {"workload": WORKLOADS[args.workload]["desc"], "lmax": lmax, "points": n, "weight_vectors": nw,
+                       "position_terms_per_step": n * T, "weight_terms_per_step": weight_terms,
+                       "tuned_n_slices": best.n_slices, "hip_graph": True},
+            "roofline": roofline}
+    if not args.no_check:
+        print("[bench] sampled parity against oracle entries (weight vectors 0 and 31)", file=sys.stderr, flush=True)
+        line["parity"] = {f"w{v}": sampled_parity(synth.Catalog(cat.theta, cat.phi, cat.w[v]), lmax, out[v])
+                          for v in (0, nw - 1)}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, weight vector 0)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline([("positions with weight vector 0",
+                                              synth.Catalog(cat.theta, cat.phi, cat.w[0]))], lmax, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +246,8 @@ def main():
     t0 = time.time()
     cats = make_catalogs(args.workload, args.scale)
     print(f"[bench] generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    if args.workload == "multi2048":
+        return run_multi(args, cats, lmax)
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
