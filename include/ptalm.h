@@ -178,6 +178,71 @@ int ptalm_prepare_call(int64_t n, int lmax, const ptalm_opts *opts);
 int ptalm_autotune(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
                    int precision, int n_weights, ptalm_opts *best, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of transforms on one device (host API).
+ *
+ * A server owns an arena of device memory (the scratch budget) and `slots`
+ * HIP streams.  Submitted requests wait in arrival order; a scheduler thread
+ * admits the oldest one as soon as a slot is free and its scratch footprint
+ * (ptalm_workspace_bytes of its call) fits in the arena, enqueues its
+ * transform (and spectrum) on the slot's stream, and frees slot and memory
+ * when the work completes.  Requests admitted while others run execute
+ * concurrently on the device.  Each request uses the work plan of the same
+ * call made alone, so its a_lm are bitwise those of the solo call.
+ * The catalog and output buffers are device memory owned by the caller: the
+ * inputs must be complete before ptalm_server_submit and stay valid, and the
+ * outputs untouched, until the request completes.
+ * ------------------------------------------------------------------------ */
+typedef struct ptalm_server ptalm_server;
+
+typedef struct ptalm_request {
+    const double *theta, *phi, *w;   /* device, n doubles each                        */
+    int64_t n;
+    int lmax;
+    int precision;                   /* PTALM_FP64, PTALM_MIXED or PTALM_FP32          */
+    double *alm;                     /* device, 2*T doubles: a_lm (output)            */
+    double *cl;                      /* device, lmax+1 doubles: C_l (output), or NULL */
+} ptalm_request;
+
+typedef struct ptalm_request_stats {
+    int status;                /* PTALM_OK or the error of the request                 */
+    int slot;                  /* stream slot it ran on                                */
+    size_t footprint_bytes;    /* arena bytes held from admission to completion        */
+    double submit_s, admit_s, done_s;   /* steady (CLOCK_MONOTONIC) clock, seconds:
+                                           submission, admission, completion seen      */
+} ptalm_request_stats;
+
+typedef struct ptalm_server_state {
+    size_t arena_bytes, arena_in_use;
+    int slots, running;
+    int64_t waiting;
+} ptalm_server_state;
+
+/* Creates a server on `device` with an arena of arena_bytes (allocated now)
+ * and 1..64 slots.  PTALM_EINVAL bad arguments; PTALM_ENOMEM arena. */
+int ptalm_server_create(int device, size_t arena_bytes, int slots, ptalm_server **out);
+
+/* Queues a request and returns at once with its ticket.  PTALM_EINVAL bad
+ * request; PTALM_EBUSY its footprint exceeds the whole arena (never admitted). */
+int ptalm_server_submit(ptalm_server *s, const ptalm_request *req, int64_t *ticket);
+
+/* *done = 1 once the request has completed; then *stats is filled, the ticket
+ * is retired and the request's status is returned. */
+int ptalm_server_poll(ptalm_server *s, int64_t ticket, int *done, ptalm_request_stats *stats);
+
+/* Blocks until the request completes; fills *stats (may be NULL), retires the
+ * ticket and returns the request's status.  One wait or final poll per ticket. */
+int ptalm_server_wait(ptalm_server *s, int64_t ticket, ptalm_request_stats *stats);
+
+/* Arena use, running and waiting requests right now. */
+int ptalm_server_query(ptalm_server *s, ptalm_server_state *state);
+
+/* Completes every queued and running request, then frees the server. */
+int ptalm_server_destroy(ptalm_server *s);
+
+/* Message of the last failed server call (or failed request) on this thread. */
+const char *ptalm_server_last_error(void);
+
 /* Message of the last failed call on this thread ("" if none). Host only. */
 const char *ptalm_last_error(void);
 

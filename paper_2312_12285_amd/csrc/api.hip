@@ -283,7 +283,7 @@ int ptalm_alm_from_points_ex(const double *theta, const double *phi, const doubl
     int rc = resolve(n, lmax, opts, &r);
     if (rc) return rc;
     const size_t need = r.precision == PTALM_BF16X3 ? multi_bytes(r, n, lmax) : partial_bytes(r, lmax);
-    if (workspace != nullptr && ws_bytes < need) return fail(PTALM_EINVAL, "workspace too small");
+    if (n > 0 && workspace != nullptr && ws_bytes < need) return fail(PTALM_EINVAL, "workspace too small");
     if (((uintptr_t)workspace & 255) != 0) return fail(PTALM_EINVAL, "workspace not 256-byte aligned");
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t T = ptalm::tri_size(lmax);

@@ -63,6 +63,34 @@ _autotune = _sig("ptalm_autotune", ctypes.c_int,
                  [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts), _vp])
 
 
+class Request(ctypes.Structure):
+    """Mirror of ``struct ptalm_request``."""
+    _fields_ = [("theta", _vp), ("phi", _vp), ("w", _vp), ("n", _i64), ("lmax", ctypes.c_int),
+                ("precision", ctypes.c_int), ("alm", _vp), ("cl", _vp)]
+
+
+class RequestStats(ctypes.Structure):
+    """Mirror of ``struct ptalm_request_stats`` (times: steady clock = time.monotonic(), seconds)."""
+    _fields_ = [("status", ctypes.c_int), ("slot", ctypes.c_int), ("footprint_bytes", ctypes.c_size_t),
+                ("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class ServerState(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("arena_in_use", ctypes.c_size_t), ("slots", ctypes.c_int),
+                ("running", ctypes.c_int), ("waiting", ctypes.c_int64)]
+
+
+_srv_create = _sig("ptalm_server_create", ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int,
+                                                          ctypes.POINTER(_vp)])
+_srv_submit = _sig("ptalm_server_submit", ctypes.c_int, [_vp, ctypes.POINTER(Request), ctypes.POINTER(_i64)])
+_srv_poll = _sig("ptalm_server_poll", ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_int),
+                                                      ctypes.POINTER(RequestStats)])
+_srv_wait = _sig("ptalm_server_wait", ctypes.c_int, [_vp, _i64, ctypes.POINTER(RequestStats)])
+_srv_query = _sig("ptalm_server_query", ctypes.c_int, [_vp, ctypes.POINTER(ServerState)])
+_srv_destroy = _sig("ptalm_server_destroy", ctypes.c_int, [_vp])
+_srv_error = _sig("ptalm_server_last_error", ctypes.c_char_p, [])
+
+
 class PtalmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"ptalm error {code}: {msg}")
@@ -211,6 +239,93 @@ def autotune(theta, phi, w, lmax: int, precision: int = FP64, stream=None) -> Op
     best = Opts()
     _check(_autotune(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, precision, nw, ctypes.byref(best), _stream(stream)))
     return best
+
+
+class Server:
+    """Continuous-batching request server of the library (ptalm_server_*): requests wait in
+    arrival order and are admitted as stream slots and arena memory free up; admitted
+    requests run concurrently on the device."""
+
+    def __init__(self, arena_bytes: int, slots: int = 4, device: int | None = None):
+        dev = torch.cuda.current_device() if device is None else device
+        h = _vp()
+        rc = _srv_create(dev, arena_bytes, slots, ctypes.byref(h))
+        if rc != PTALM_OK:
+            raise PtalmError(rc, _srv_error().decode())
+        self._h = h
+        self._keep = {}        # ticket -> tensors the request reads or writes
+
+    def submit(self, theta, phi, w, lmax: int, precision: int = FP64, alm=None, cl=None):
+        """Queue one catalog (device tensors, complete on the current stream: it is
+        synchronized first).  Returns (ticket, alm, cl)."""
+        _dev_f64(theta, "theta"); _dev_f64(phi, "phi"); _dev_f64(w, "w")
+        n = theta.numel()
+        if phi.numel() != n or w.numel() != n:
+            raise ValueError("theta, phi and w must have the same length")
+        T = alm_size(lmax)
+        if alm is None:
+            alm = torch.empty(2 * T, dtype=torch.float64, device=theta.device)
+        if cl is False:
+            cl = None
+        elif cl is None:
+            cl = torch.empty(lmax + 1, dtype=torch.float64, device=theta.device)
+        torch.cuda.current_stream().synchronize()
+        req = Request(theta.data_ptr(), phi.data_ptr(), w.data_ptr(), n, lmax, precision, alm.data_ptr(),
+                      None if cl is None else cl.data_ptr())
+        t = _i64()
+        rc = _srv_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if rc != PTALM_OK:
+            raise PtalmError(rc, _srv_error().decode())
+        self._keep[t.value] = (theta, phi, w, alm, cl)
+        return t.value, alm, cl
+
+    def poll(self, ticket: int):
+        """None while running; the stats (RequestStats) once done."""
+        done = ctypes.c_int()
+        st = RequestStats()
+        rc = _srv_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(st))
+        if not done.value and rc == PTALM_OK:
+            return None
+        self._keep.pop(ticket, None)
+        if rc != PTALM_OK:
+            raise PtalmError(rc, _srv_error().decode())
+        return st
+
+    def wait(self, ticket: int):
+        st = RequestStats()
+        rc = _srv_wait(self._h, ticket, ctypes.byref(st))
+        self._keep.pop(ticket, None)
+        if rc != PTALM_OK:
+            raise PtalmError(rc, _srv_error().decode())
+        return st
+
+    def state(self) -> ServerState:
+        st = ServerState()
+        _check_srv(_srv_query(self._h, ctypes.byref(st)))
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _srv_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_srv(rc):
+    if rc != PTALM_OK:
+        raise PtalmError(rc, _srv_error().decode())
 
 
 def release_cache():
