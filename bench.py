@@ -15,6 +15,11 @@ Workloads (--workload):
   multi2048    1e7 masked positions shared by 32 lognormal weight vectors, lmax 2048,
                split-bf16 MFMA form; tuned by the library's autotuner on a prefix,
                then each step replays one captured HIP graph (transform + 32 spectra)
+  served       a Poisson stream (50/s) of 500 masked catalogs, n log-uniform in
+               [1e4, 1e7], lmax uniform in {128, ..., 2048}, through the library's
+               request server; value = terms/s of the stream, with p50/p99 latency,
+               the same trace time-scaled to 0.7x the measured capacity, and a
+               burst of the first 100 requests served vs run one after another
 
 Besides value, the line carries the roofline of the transform kernel (its
 algorithmic FP64 work, 7 flops per term, over its device time measured with
@@ -44,6 +49,8 @@ WORKLOADS = {
     "galaxies1024": dict(desc="masked galaxies n=2e6 (2% jittered copies, lognormal sigma=0.3) + masked randoms "
                               "n=2e7, lmax=1024, C_l of galaxies - alpha randoms and W_l", lmax=1024),
     "fullsky64": dict(desc="full-sky uniform n=1e4, unit weights, lmax=64", lmax=64),
+    "served": dict(desc="Poisson stream 50/s of masked catalogs, n log-uniform [1e4, 1e7], lmax uniform in "
+                        "{128,256,512,1024,2048}, lognormal sigma=0.3 weights, through the request server", lmax=2048),
     "multi2048": dict(desc="one masked position set n=1e7 shared by 32 lognormal weight vectors (sigma=0.2), "
                            "lmax=2048, split-bf16 MFMA form", lmax=2048),
 }
@@ -213,6 +220,120 @@ def run_multi(args, cats, lmax):
     print(json.dumps(line), flush=True)
 
 
+def _served_catalogs(reqs, workers):
+    """Host generation of every request's catalog in a fork pool (before the GPU is touched)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    from paper_2312_12285_amd import synth
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(synth.served_catalog, reqs, chunksize=2))
+
+
+def run_served(args):
+    """served: replay the request trace through ptalm.Server (see the module docstring)."""
+    import numpy as np
+    from paper_2312_12285_amd import synth
+    K = args.served_requests
+    reqs = synth.served_trace(K, 50.0, 51)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.time()
+    cats = _served_catalogs(reqs, workers)
+    print(f"[bench] generated {K} catalogs ({sum(r.n for r in reqs):.3g} points) in {time.time() - t0:.1f} s "
+          f"with {workers} processes", file=sys.stderr, flush=True)
+    import torch
+    from paper_2312_12285_amd import ptalm
+    prec = {"fp64": ptalm.FP64, "mixed": ptalm.MIXED, "fp32": ptalm.FP32}[args.precision]
+    dev = [(torch.as_tensor(c.theta).cuda(), torch.as_tensor(c.phi).cuda(), torch.as_tensor(c.w).cuda())
+           for c in cats]
+    outs = [(torch.empty(2 * tri(r.lmax), dtype=torch.float64, device="cuda"),
+             torch.empty(r.lmax + 1, dtype=torch.float64, device="cuda")) for r in reqs]
+    for lmax in sorted({r.lmax for r in reqs}):
+        ptalm.prepare(lmax)
+    torch.cuda.synchronize()
+    terms = np.array([r.n * tri(r.lmax) for r in reqs], dtype=np.float64)
+    arena = int(args.served_arena_gb * (1 << 30))
+
+    def replay(arrivals, order, label):
+        with ptalm.Server(arena_bytes=arena, slots=args.served_slots) as srv:
+            start = time.monotonic()
+            tickets = {}
+            last_note = start
+            for k in order:
+                dt = start + arrivals[k] - time.monotonic()
+                if dt > 0:
+                    time.sleep(dt)
+                t, p, w = dev[k]
+                tickets[k] = srv.submit(t, p, w, reqs[k].lmax, precision=prec, alm=outs[k][0], cl=outs[k][1])[0]
+                if time.monotonic() - last_note > 15:
+                    last_note = time.monotonic()
+                    print(f"[bench] {label}: submitted {len(tickets)}/{len(order)}", file=sys.stderr, flush=True)
+            stats = {}
+            while len(stats) < len(order):
+                for k in order:
+                    if k not in stats:
+                        st = srv.poll(tickets[k])
+                        if st is not None:
+                            stats[k] = st
+                time.sleep(0.002)
+                if time.monotonic() - last_note > 15:
+                    last_note = time.monotonic()
+                    print(f"[bench] {label}: completed {len(stats)}/{len(order)}", file=sys.stderr, flush=True)
+        lat = np.array([stats[k].done_s - (start + arrivals[k]) for k in order])
+        makespan = max(stats[k].done_s for k in order) - start
+        tot = float(terms[order].sum())
+        print(f"[bench] {label}: makespan {makespan:.1f} s, {tot / makespan:.3e} terms/s", file=sys.stderr, flush=True)
+        return {"requests": len(order), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "makespan_s": round(makespan, 3),
+                "terms_per_s": tot / makespan,
+                "offered_terms_per_s": tot / max(1e-9, float(arrivals[order].max() - arrivals[order].min())),
+                "max_queue_wait_s": round(float(max(stats[k].admit_s - (start + arrivals[k]) for k in order)), 4)}
+
+    arrivals = np.array([r.arrival_s for r in reqs])
+    order = list(range(K))
+    res = replay(arrivals, order, "trace at 50/s")
+    capacity = res["terms_per_s"]
+    offered = float(terms.sum() / arrivals.max())
+    scale = offered / (0.7 * capacity)
+    res_07 = replay(arrivals * scale, order, "trace time-scaled to 0.7x capacity")
+    res_07["time_scale"] = round(scale, 4)
+
+    B = min(100, K)
+    burst = replay(np.zeros(K), list(range(B)), f"burst of the first {B}")
+    served_alms = {k: outs[k][0].clone() for k in range(B)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(B):
+        t, p, w = dev[k]
+        ptalm.alm_from_points(t, p, w, reqs[k].lmax, out=outs[k][0], options=ptalm.opts(precision=prec))
+        ptalm.cl_from_alm(outs[k][0], reqs[k].lmax, out=outs[k][1])
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    same = sum(bool(torch.equal(served_alms[k], outs[k][0])) for k in range(B))
+    seq_rate = float(terms[:B].sum()) / seq_s
+    print(f"[bench] sequential {B}: {seq_s:.1f} s; served == solo for {same}/{B}", file=sys.stderr, flush=True)
+
+    line = {"metric": METRIC, "value": capacity, "unit": UNIT, "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": round(1e3 * res["makespan_s"], 1), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": {"fp64": "f64", "mixed": "f64 recurrence + f32 products",
+                                           "fp32": "f32 + f64"}[args.precision], "data": "synthetic",
+            "config": {"workload": WORKLOADS["served"]["desc"], "requests": K, "rate_hz": 50.0,
+                       "points": int(sum(r.n for r in reqs)), "terms": float(terms.sum()), "slots": args.served_slots,
+                       "arena_bytes": arena, "precision": args.precision},
+            "served": {"trace_50hz": res, "trace_0.7x_capacity": res_07,
+                       "burst": {"requests": B, "served_terms_per_s": burst["terms_per_s"],
+                                 "sequential_terms_per_s": seq_rate,
+                                 "served_over_sequential": round(burst["terms_per_s"] / seq_rate, 4),
+                                 "served_equals_solo": f"{same}/{B} bitwise"}},
+            "roofline": {"bound": "alu", "achieved": round(FLOPS_PER_TERM * capacity / 1e12, 3),
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(FLOPS_PER_TERM * capacity / 1e12 / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                         "kernel": "alm_direct_kernel (all requests; aggregate over concurrent launches)"}}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, request 0)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline([("request 0", cats[0])], reqs[0].lmax, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +347,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=500)
+    ap.add_argument("--served-slots", type=int, default=4)
+    ap.add_argument("--served-arena-gb", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter runs scale FETCH/WRITE_SIZE by it)")
     args = ap.parse_args()
@@ -234,6 +358,8 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
               "in DESIGN.md, not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "served":        # generates its catalogs in worker processes before touching the GPU
+        return run_served(args)
 
     import numpy as np
     import torch
