@@ -143,6 +143,37 @@ def sampled_parity(cat, lmax, alm_dev):
             "oracle_seconds": round(dt, 1)}
 
 
+def per_l_errors(got, ref, lmax):
+    """Per-l norm-wise relative error over m, the global norm-wise error, and a few l."""
+    import numpy as np
+    L = np.concatenate([np.arange(m, lmax + 1) for m in range(lmax + 1)])
+    num = np.bincount(L, weights=np.abs(got - ref) ** 2, minlength=lmax + 1)
+    den = np.bincount(L, weights=np.abs(ref) ** 2, minlength=lmax + 1)
+    per_l = np.sqrt(num / np.maximum(den, 1e-300))
+    pick = sorted({0, 1, 10, 100, lmax // 4, lmax // 2, lmax})
+    return {"global": float(np.sqrt(num.sum() / den.sum())), "max_per_l": float(per_l.max()),
+            "l_of_max": int(per_l.argmax()), "per_l": {str(l): float(per_l[l]) for l in pick}}
+
+
+def precision_errors(args, cat, lmax, alm_dev, prec):
+    """Error of a reduced-precision result: against the FP64 GPU path on the full catalog
+    (itself gated against the oracle), and against the oracle on the first 1e4 points."""
+    import numpy as np
+    import torch
+    from oracle import ref
+    from paper_2312_12285_amd import ptalm
+    t = torch.as_tensor(cat.theta).cuda(); p = torch.as_tensor(cat.phi).cuda(); w = torch.as_tensor(cat.w).cuda()
+    full64 = ptalm.alm_from_points(t, p, w, lmax)
+    got = ptalm.as_complex(alm_dev).cpu().numpy()
+    out = {"vs_fp64_gpu_full_catalog": per_l_errors(got, ptalm.as_complex(full64).cpu().numpy(), lmax)}
+    k = min(cat.n, 10_000)
+    sub = ptalm.alm_from_points(t[:k].contiguous(), p[:k].contiguous(), w[:k].contiguous(), lmax,
+                                options=ptalm.opts(precision=prec))
+    want = ref.alm_from_points(cat.theta[:k], cat.phi[:k], cat.w[:k], lmax)
+    out[f"vs_oracle_first_{k}_points"] = per_l_errors(ptalm.as_complex(sub).cpu().numpy(), want, lmax)
+    return out
+
+
 def run_multi(args, cats, lmax):
     """multi2048: autotune on a prefix, capture transform + spectra once, replay per step."""
     import numpy as np
@@ -444,6 +475,9 @@ def main():
     if not args.no_check:
         print("[bench] sampled parity against oracle entries", file=sys.stderr, flush=True)
         line["parity"] = sampled_parity(cats[-1][1], lmax, outs[-1])
+        if prec != ptalm.FP64:
+            print("[bench] precision error against the FP64 path and the oracle", file=sys.stderr, flush=True)
+            line["precision_error"] = precision_errors(args, cats[-1][1], lmax, outs[-1], prec)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cats, lmax, args.cpu_seconds)

@@ -144,7 +144,7 @@ constexpr int kDefaultLB = 16;
 constexpr int kDefaultMode = 3;  // register butterfly stage + pipelined reduction
 constexpr int kMixedKP = 8;   // 238 VGPRs: two wavefronts per SIMD
 constexpr int kFp32KP = 10;
-constexpr int kTargetItems = 8192;   // (slice, range) items: ~4 per resident wavefront
+constexpr int kTargetItems = 65536;  // (slice, range) items: ~32 per resident wavefront (finer items shorten the tail)
 constexpr int kMaxSlices = 32;
 constexpr int64_t kMaxItems = int64_t(1) << 22;   // workgroups of one launch (x 512 threads < 2^32)
 
