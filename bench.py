@@ -57,13 +57,17 @@ WORKLOADS = {
 
 
 PROFILES = os.path.join(HERE, "profiles")
-KERNEL_SOURCE = os.path.join(HERE, "paper_2312_12285_amd", "csrc", "alm_direct.hip")
+# the kernel and the work plan that decides its launch (a change to either voids recorded traffic)
+KERNEL_SOURCES = [os.path.join(HERE, "paper_2312_12285_amd", "csrc", f) for f in ("alm_direct.hip", "api.hip")]
 
 
 def kernel_source_hash():
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(workload, variant):
