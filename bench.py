@@ -407,14 +407,14 @@ def main():
     t0 = time.time()
     cats = make_catalogs(args.workload, args.scale)
     print(f"[bench] generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    if args.workload == "multi2048":
-        return run_multi(args, cats, lmax)
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "multi2048":
+        return run_multi(args, cats, lmax)
     dev = []
     for name, c in cats:
         dev.append((name, torch.as_tensor(c.theta).cuda(), torch.as_tensor(c.phi).cuda(),
