@@ -1,0 +1,144 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch configurations bench.py times.
+
+The oracle cannot evaluate every a_lm of these catalogs (1e12-1e14 terms); it
+computes sampled coefficients one by one over every point
+(ptalm_ref_alm_entries), and properties that hold at any size complete the check:
+
+* galaxies 2e6 + randoms 2e7 at lmax 1024 (the two-catalog workload): sampled
+  entries of both transforms, the monopole a_00 = sum w / sqrt(4 pi), alpha of
+  the FKP field, and linearity (the transform of the catalog equals the sum of
+  the transforms of its two halves);
+* the first 1e7 of the 1e8 masked randoms at lmax 3072, in the launch
+  configuration of the full catalog (32 point slices x 2048 m-ranges, 6 points
+  per lane, 16-l blocks): sampled entries, linearity, and the mixed form against
+  FP64 (global <= 1e-6);
+* 1e7 positions x 32 weight vectors at lmax 2048 in the split-bf16 MFMA form:
+  sampled entries of two weight vectors (<= 1e-4 of the l-rms) and weight vector
+  0 against the FP64 path over all coefficients (global <= 1e-4).
+
+Sampled entries are compared against the rms of the coefficients at their l,
+sqrt(C_l), as the bench does.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import per_l_rel_err
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2312_12285_amd import ptalm
+    return ptalm
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(*arrs):
+    import torch
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def entries(lmax):
+    return [(0, 0), (1, 0), (1, 1), (2, 1), (30, 7), (64, 60), (lmax // 2, lmax // 2 - 3),
+            (lmax, lmax), (lmax, lmax - 1), (lmax, lmax - 5)]
+
+
+def check_entries(lib, oracle, cat_theta, cat_phi, cat_w, lmax, alm_dev, tol, what):
+    pairs = entries(lmax)
+    ls = np.array([p[0] for p in pairs]); ms = np.array([p[1] for p in pairs])
+    want = oracle.alm_entries(cat_theta, cat_phi, cat_w, ls, ms)
+    a = lib.as_complex(alm_dev).cpu().numpy()
+    got = np.array([a[lib.alm_index(lmax, l, m)] for l, m in pairs])
+    cl = lib.cl_from_alm(alm_dev, lmax).cpu().numpy()
+    rel = np.abs(got - want) / np.sqrt(cl[ls])
+    say(f"{what}: sampled entries, max |err| / rms_l = {rel.max():.3e}")
+    assert rel.max() <= tol
+
+
+def linear_split(lib, t, p, w, lmax, whole, tol, what, **opt):
+    import torch
+    h = t.numel() // 2
+    o = lib.opts(**opt) if opt else None
+    a1 = lib.alm_from_points(t[:h].contiguous(), p[:h].contiguous(), w[:h].contiguous(), lmax, options=o)
+    a2 = lib.alm_from_points(t[h:].contiguous(), p[h:].contiguous(), w[h:].contiguous(), lmax, options=o)
+    torch.cuda.synchronize()
+    s = lib.as_complex(a1).cpu().numpy() + lib.as_complex(a2).cpu().numpy()
+    err = per_l_rel_err(s, lib.as_complex(whole).cpu().numpy(), lmax)
+    say(f"{what}: linearity, max per-l err {err.max():.3e}")
+    assert err.max() <= tol
+
+
+def test_two_catalog_workload_full_size(lib, oracle):
+    import torch
+    from paper_2312_12285_amd.synth import masked_galaxies, masked_randoms
+    lmax = 1024
+    say("case: galaxies 2e6 + randoms 2e7, lmax 1024")
+    g = masked_galaxies(2_000_000, seed_pos=21, seed_w=22)
+    r = masked_randoms(20_000_000, seed=23)
+    tg, pg, wg = dev(g.theta, g.phi, g.w)
+    tr, pr, wr = dev(r.theta, r.phi, r.w)
+    ag = lib.alm_from_points(tg, pg, wg, lmax)
+    ar = lib.alm_from_points(tr, pr, wr, lmax)
+    torch.cuda.synchronize()
+    check_entries(lib, oracle, g.theta, g.phi, g.w, lmax, ag, 1e-10, "galaxies")
+    check_entries(lib, oracle, r.theta, r.phi, r.w, lmax, ar, 1e-10, "randoms")
+    for a, cat in ((ag, g), (ar, r)):
+        a00 = a[0].item()
+        assert abs(a00 - math.fsum(cat.w) / math.sqrt(4 * math.pi)) <= 1e-13 * abs(a00)
+        assert a[1].item() == 0.0
+    delta, window, alpha = lib.fkp_fields(ag, ar, lmax)
+    assert abs(alpha.item() - math.fsum(g.w) / math.fsum(r.w)) <= 1e-12 * alpha.item()
+    cl = lib.cl_from_alm(delta, lmax).cpu().numpy()
+    assert np.all(cl >= 0) and np.all(np.isfinite(cl))
+    linear_split(lib, tg, pg, wg, lmax, ag, 1e-12, "galaxies")
+
+
+def test_randoms_lmax3072_bench_launch_configuration(lib, oracle):
+    import torch
+    from paper_2312_12285_amd.synth import masked_randoms
+    lmax, n = 3072, 10_000_000
+    say("case: first 1e7 of the 1e8 masked randoms, lmax 3072")
+    r = masked_randoms(n, seed=31)
+    t, p, w = dev(r.theta, r.phi, r.w)
+    a = lib.alm_from_points(t, p, w, lmax)
+    torch.cuda.synchronize()
+    check_entries(lib, oracle, r.theta, r.phi, r.w, lmax, a, 1e-10, "randoms 1e7")
+    linear_split(lib, t, p, w, lmax, a, 1e-12, "randoms 1e7")
+    mixed = lib.alm_from_points(t, p, w, lmax, options=lib.opts(precision=lib.MIXED))
+    torch.cuda.synchronize()
+    am = lib.as_complex(mixed).cpu().numpy()
+    a64 = lib.as_complex(a).cpu().numpy()
+    g = np.linalg.norm(am - a64) / np.linalg.norm(a64)
+    say(f"mixed vs FP64 at 1e7 points: global {g:.3e}, max per-l {per_l_rel_err(am, a64, lmax).max():.3e}")
+    assert g <= 1e-6
+
+
+def test_multi_weight_full_size(lib, oracle):
+    import torch
+    from paper_2312_12285_amd.synth import multi_weight_positions
+    lmax = 2048
+    say("case: 1e7 positions x 32 weight vectors, lmax 2048, split-bf16 MFMA")
+    th, ph, W = multi_weight_positions(10_000_000, 32, seed_pos=41, seed_w0=4100)
+    t, p, w = dev(th, ph, W)
+    out = lib.alm_from_points(t, p, w, lmax, options=lib.opts(precision=lib.BF16X3))
+    torch.cuda.synchronize()
+    for v in (0, 31):
+        check_entries(lib, oracle, th, ph, W[v], lmax, out[v], 1e-4, f"bf16x3 weight vector {v}")
+    a64 = lib.alm_from_points(t, p, w[0].contiguous(), lmax)
+    torch.cuda.synchronize()
+    x = lib.as_complex(out[0]).cpu().numpy()
+    y = lib.as_complex(a64).cpu().numpy()
+    g = np.linalg.norm(x - y) / np.linalg.norm(y)
+    say(f"bf16x3 vs FP64, weight vector 0: global {g:.3e}")
+    assert g <= 1e-4
