@@ -265,6 +265,8 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
             // K-step's A fragments are read one K-step ahead.
 #pragma unroll
             for (int i = 0; i < kLT / 2; ++i) {
+                // the MFMAs issue at raised wave priority, the recurrence at normal
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int u = i * kUnits / (kLT / 2); u < (i + 1) * kUnits / (kLT / 2); ++u) {
                     const int ks = u / NTW, n = u % NTW;
@@ -276,6 +278,7 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
                     d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_h[ks], bl[n][ks], d[n], 0, 0, 0);
                     d[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa_l[ks], bh[n][ks], d[n], 0, 0, 0);
                 }
+                __builtin_amdgcn_s_setprio(0);
                 recur_pair(cf[2 * i], cf[2 * i + 1], 2 * i, b ^ 1);
                 __builtin_amdgcn_sched_barrier(0);
             }
