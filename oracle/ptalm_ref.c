@@ -358,3 +358,42 @@ int ptalm_ref_cross_cl(const double *alm1, const double *alm2, int lmax, double 
 
 /* keep tri_size referenced for callers that size buffers from the header's formula */
 int64_t ptalm_ref_alm_size(int lmax) { return lmax < 0 ? 0 : tri_size(lmax); }
+
+/* ---------------------------------------------------------------------------
+ * Mode coupling (Sec. 2.1 eq. chat) and the 3j symbols it needs (App. C).
+ * ------------------------------------------------------------------------- */
+
+static long double lfact(int k) { return lgammal((long double)k + 1.0L); }
+
+double ptalm_ref_threej000(int l1, int l2, int l3)
+{
+    if (l1 < 0 || l2 < 0 || l3 < 0) return 0.0;
+    const int L = l1 + l2 + l3;
+    if (L & 1) return 0.0;
+    if (l1 > l2 + l3 || l2 > l1 + l3 || l3 > l1 + l2) return 0.0;
+    const int h = L / 2;
+    const long double lg = 0.5L * (lfact(L - 2 * l1) + lfact(L - 2 * l2) + lfact(L - 2 * l3) - lfact(L + 1))
+                         + lfact(h) - lfact(h - l1) - lfact(h - l2) - lfact(h - l3);
+    const long double v = expl(lg);
+    return (double)((h & 1) ? -v : v);
+}
+
+int ptalm_ref_coupling_matrix(const double *Wl, int lmax_w, int lmax, double *M, int nthreads)
+{
+    if (Wl == NULL || M == NULL || lmax < 0 || lmax_w < 0) return -1;
+    const long double inv4pi = 1.0L / (4.0L * 3.14159265358979323846264338327950288L);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+    for (int l = 0; l <= lmax; ++l) {
+        for (int lp = 0; lp <= lmax; ++lp) {
+            long double sum = 0.0L;
+            const int lo = l > lp ? l - lp : lp - l;
+            const int hi = l + lp < lmax_w ? l + lp : lmax_w;
+            for (int lam = lo; lam <= hi; lam += 2) {
+                const long double t = (long double)ptalm_ref_threej000(l, lp, lam);
+                sum += (2.0L * lam + 1.0L) * t * t * (long double)Wl[lam];
+            }
+            M[(int64_t)l * (lmax + 1) + lp] = (double)((2.0L * lp + 1.0L) * inv4pi * sum);
+        }
+    }
+    return 0;
+}

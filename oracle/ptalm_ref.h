@@ -52,6 +52,20 @@ int ptalm_ref_cl_from_alm(const double *alm, int lmax, double *cl);
 /* Cross spectrum C^AB_l = (2l+1)^-1 sum_{m=-l..l} Re(a_lm conj(b_lm)). */
 int ptalm_ref_cross_cl(const double *alm1, const double *alm2, int lmax, double *cl);
 
+/* Wigner 3j symbol (l1 l2 l3; 0 0 0) (App. C), from its closed form for zero
+ * projections evaluated in long double with log-gamma:
+ *   (-1)^(L/2) sqrt[(L-2l1)! (L-2l2)! (L-2l3)! / (L+1)!] (L/2)! / [(L/2-l1)! (L/2-l2)! (L/2-l3)!],
+ * L = l1+l2+l3; 0 when L is odd or the triangle condition fails. */
+double ptalm_ref_threej000(int l1, int l2, int l3);
+
+/* Mode-coupling matrix of eq. chat (Sec. 2.1):
+ *   M[l][l'] = (2l'+1)/(4 pi) sum_lambda (2 lambda + 1) (l l' lambda; 0 0 0)^2 W_lambda,
+ * for 0 <= l, l' <= lmax, the sum over lambda <= lmax_w (W_lambda, lambda <= lmax_w,
+ * given; larger lambda taken as 0).  M is (lmax+1)^2 doubles, row-major in l.
+ * 3j values from ptalm_ref_threej000, sums in long double in lambda order;
+ * parallel over l.  Returns 0, or -1 on bad arguments. */
+int ptalm_ref_coupling_matrix(const double *Wl, int lmax_w, int lmax, double *M, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

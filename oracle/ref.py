@@ -26,8 +26,11 @@ def _bind(path):
     lib.ptalm_ref_cross_cl.argtypes = [_dp, _dp, ctypes.c_int, _dp]
     lib.ptalm_ref_alm_size.argtypes = [ctypes.c_int]
     lib.ptalm_ref_alm_size.restype = ctypes.c_int64
+    lib.ptalm_ref_threej000.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.ptalm_ref_threej000.restype = ctypes.c_double
+    lib.ptalm_ref_coupling_matrix.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
     for f in ("ptalm_ref_alm_from_points", "ptalm_ref_alm_from_points_ld", "ptalm_ref_alm_entries",
-              "ptalm_ref_cl_from_alm", "ptalm_ref_cross_cl"):
+              "ptalm_ref_cl_from_alm", "ptalm_ref_cross_cl", "ptalm_ref_coupling_matrix"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -136,3 +139,56 @@ def cross_cl(alm1, alm2, lmax: int) -> np.ndarray:
     if lib.ptalm_ref_cross_cl(_ptr(a), _ptr(b), lmax, _ptr(out)) != 0:
         raise ValueError("bad arguments")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Mode coupling and bandpowers (Sec. 2.1 eq. chat, eq. mode_coupling; App. C)
+# ---------------------------------------------------------------------------
+
+def threej000(l1: int, l2: int, l3: int) -> float:
+    """(l1 l2 l3; 0 0 0), closed form (App. C)."""
+    return float(_load().ptalm_ref_threej000(int(l1), int(l2), int(l3)))
+
+
+def coupling_matrix(Wl, lmax: int, nthreads: int = 0) -> np.ndarray:
+    """M[l, l'] = (2l'+1)/(4pi) sum_lambda (2 lambda+1) (l l' lambda; 000)^2 W_lambda (eq. chat),
+    0 <= l, l' <= lmax; W given for lambda = 0..len(Wl)-1."""
+    Wl = _f64(Wl)
+    M = np.zeros((lmax + 1, lmax + 1))
+    rc = _load().ptalm_ref_coupling_matrix(_ptr(Wl), Wl.size - 1, lmax, _ptr(M), nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return M
+
+
+def bin_matrix(lmax: int, delta_l: int, lmin: int = 0):
+    """theta[b, l] = 1/delta_l for l in bin b = [lmin + b delta_l, lmin + (b+1) delta_l) (complete
+    bins within lmax only), else 0 (Sec. 2.1: averaging C_l within each bin); and the bin
+    indicator chi[l, b]."""
+    nb = (lmax + 1 - lmin) // delta_l
+    theta = np.zeros((nb, lmax + 1))
+    chi = np.zeros((lmax + 1, nb))
+    for b in range(nb):
+        lo = lmin + b * delta_l
+        theta[b, lo:lo + delta_l] = 1.0 / delta_l
+        chi[lo:lo + delta_l, b] = 1.0
+    return theta, chi
+
+
+def decoupled_bandpowers(cl_hat, M, theta, chi):
+    """Mode-decoupled bandpowers (eq. mode_coupling): M_bb' = sum_{l in b} sum_{l' in b'}
+    theta_b^l M_ll', C~_b = sum_b' (M^-1)_bb' C^_b' with C^_b = sum_l theta_b^l C^_l, and the
+    window of eq. expectation_value, cal M_bl' = sum_b' (M^-1)_bb' sum_l theta_b'^l M_ll'."""
+    Mbb = theta @ M @ chi
+    cb = np.linalg.solve(Mbb, theta @ np.asarray(cl_hat))
+    window = np.linalg.solve(Mbb, theta @ M)
+    return cb, window, Mbb
+
+
+def normalized_bandpowers(cl_hat, M, theta, Wl):
+    """Normalised convention: C~'_b = N sum_l theta_b^l C^_l, cal M'_bl' = N sum_l theta_b^l M_ll',
+    with 1/N = sum_l' (2l'+1)/(4pi) W_l' (the shot-noise amplitude factor)."""
+    Wl = np.asarray(Wl, dtype=np.float64)
+    lam = np.arange(Wl.size)
+    N = 1.0 / np.sum((2 * lam + 1) / (4 * np.pi) * Wl)
+    return N * (theta @ np.asarray(cl_hat)), N * (theta @ M), N

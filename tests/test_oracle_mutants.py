@@ -91,3 +91,47 @@ def test_planted_mistake_is_caught(name, tmp_path):
                     str(tmp_path / "ptalm_ref.c"), "-lm"], check=True)
     with ref.use_library(str(so)):
         assert not run_pins(), f"planted mistake {name!r} passed every pin"
+
+
+COUPLING_MUTANTS = {
+    "threej_sign_lost": ("return (double)((h & 1) ? -v : v);", "return (double)v;"),
+    "threej_factorial_wrong": ("- lfact(L + 1))", "- lfact(L))"),
+    "coupling_lambda_weight_dropped": ("sum += (2.0L * lam + 1.0L) * t * t * (long double)Wl[lam];",
+                                       "sum += t * t * (long double)Wl[lam];"),
+    "coupling_wrong_degree_factor": ("(double)((2.0L * lp + 1.0L) * inv4pi * sum)", "(double)((2.0L * l + 1.0L) * inv4pi * sum)"),
+    "coupling_lambda_range_short": ("const int hi = l + lp < lmax_w ? l + lp : lmax_w;",
+                                    "const int hi = l + lp < lmax_w ? l + lp : lmax_w - 1;"),
+}
+
+
+def run_coupling_pins():
+    """The coupling pin battery of test_oracle_coupling; True if all pass."""
+    import test_oracle_coupling as t
+    checks = [t.test_threej_textbook_values, t.test_threej_paper_terminal_and_recurrence,
+              t.test_threej_gaunt_integral_quadrature, t.test_threej_orthogonality,
+              t.test_coupling_full_sky_is_identity, t.test_coupling_row_sums_shot_noise_bracket,
+              t.test_coupling_equals_its_definition_by_quadrature]
+    for c in checks:
+        try:
+            c(ref)
+        except AssertionError:
+            return False
+    return True
+
+
+def test_real_oracle_passes_coupling_battery():
+    assert run_coupling_pins()
+
+
+@pytest.mark.parametrize("name", sorted(COUPLING_MUTANTS))
+def test_planted_coupling_mistake_is_caught(name, tmp_path):
+    old, new = COUPLING_MUTANTS[name]
+    src = open(os.path.join(ORACLE_DIR, "ptalm_ref.c")).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique in the oracle source"
+    shutil.copy(os.path.join(ORACLE_DIR, "ptalm_ref.h"), tmp_path / "ptalm_ref.h")
+    (tmp_path / "ptalm_ref.c").write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(so),
+                    str(tmp_path / "ptalm_ref.c"), "-lm"], check=True)
+    with ref.use_library(str(so)):
+        assert not run_coupling_pins(), f"planted mistake {name!r} passed every coupling pin"
