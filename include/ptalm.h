@@ -148,6 +148,45 @@ int ptalm_alm_axpy(double alpha, const double *x, double *y, int lmax, void *str
 int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax,
                      double *delta, double *window, double *alpha_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Mode coupling and bandpowers (Sec. 2.1 eq. chat, eq. mode_coupling,
+ * eq. expectation_value; 3j symbols of App. C).  Device pointers, async on
+ * `stream`.
+ * ------------------------------------------------------------------------ */
+
+/* Shot noise of a weighted point set: out[0] = a^2 sum_i w_i^2 / (4 pi) with
+ * a = alpha[0] (device) or 1 if alpha is NULL; for the window of scaled
+ * randoms (the footnote to eq. wldef).  Fixed summation order. */
+int ptalm_window_shot_noise(const double *w, int64_t n, const double *alpha, double *out, void *stream);
+
+/* Mode-coupling matrix
+ *   M[l][l'] = (2l'+1)/(4 pi) sum_lambda (2 lambda+1) (l l' lambda; 0 0 0)^2 W_lambda   (eq. chat)
+ *   Wl    : lmax_w+1 doubles, the window spectrum W_lambda (eq. wldef; lambda > lmax_w
+ *           counts as 0; W up to 2 lmax gives the complete matrix);
+ *   shot  : NULL, or one device double subtracted from every W_lambda first;
+ *   M     : (lmax+1)^2 doubles, row-major in l (output).
+ * FP64, one thread per (l, l'); the 3j squares come from the recurrences of
+ * App. C without square roots.  PTALM_EINVAL on bad sizes or NULL pointers. */
+int ptalm_coupling_matrix(const double *Wl, int lmax_w, const double *shot, int lmax, double *M, void *stream);
+
+/* Number of complete bins [lmin + b delta_l, lmin + (b+1) delta_l) within lmax (0 if none). Host only. */
+int ptalm_bandpower_count(int lmax, int lmin, int delta_l);
+
+/* Bandpowers of a pseudo-spectrum cl_hat[0..lmax] with theta_b^l = 1/delta_l on
+ * those bins (Sec. 2.1):
+ *   mode 0, mode-decoupled (eq. mode_coupling): cb = Mbb^-1 theta cl_hat with
+ *     Mbb[b][b'] = sum_{l in b} sum_{l' in b'} theta_b^l M[l][l'], and
+ *     window = Mbb^-1 theta M (eq. expectation_value), by Gauss-Jordan
+ *     elimination with partial pivoting in FP64 (a singular Mbb, from bins too
+ *     narrow for the mask, gives non-finite output);
+ *   mode 1, normalised: cb = N theta cl_hat, window = N theta M with
+ *     1/N = sum_l (2l+1) W_l / (4 pi) (needs Wl, lmax_w).
+ * cb: nb doubles, window: nb x (lmax+1) doubles row-major (may be NULL).
+ * Allocates stream-ordered scratch.  PTALM_EINVAL: no complete bin, more than
+ * 1024 bins, bad mode, NULL inputs. */
+int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, int lmax_w, int lmax, int lmin,
+                     int delta_l, int mode, double *cb, double *window, void *stream);
+
 /* Device time of the transform kernel(s) of the last ptalm_alm_from_points_ex
  * call made on this thread with opts->timing set: from just before the first
  * transform kernel to just after the last one, on that call's stream.  Blocks

@@ -428,6 +428,58 @@ int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax
     return e == hipSuccess ? PTALM_OK : fail_hip(e, "fkp kernel launch");
 }
 
+int ptalm_window_shot_noise(const double *w, int64_t n, const double *alpha, double *out, void *stream) {
+    g_error.clear();
+    if (n < 0) return fail(PTALM_EINVAL, "n < 0");
+    if (out == nullptr || (n > 0 && w == nullptr)) return fail(PTALM_EINVAL, "NULL pointer");
+    hipError_t e = ptalm::launch_shot_noise(w, n, alpha, out, (hipStream_t)stream);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "shot-noise kernel launch");
+}
+
+int ptalm_coupling_matrix(const double *Wl, int lmax_w, const double *shot, int lmax, double *M, void *stream_) {
+    g_error.clear();
+    if (!lmax_ok(lmax) || lmax_w < 0 || lmax_w > 2 * PTALM_LMAX_MAX + 1) return fail(PTALM_EINVAL, "lmax out of range");
+    if (Wl == nullptr || M == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    hipStream_t stream = (hipStream_t)stream_;
+    double *wtmp = nullptr;
+    hipError_t e;
+    if (shot != nullptr && (e = hipMallocAsync((void **)&wtmp, sizeof(double) * (lmax_w + 1), stream)) != hipSuccess)
+        return fail_hip(e, "hipMallocAsync");
+    e = ptalm::launch_coupling(Wl, lmax_w, shot, wtmp, lmax, M, stream);
+    int rc = e == hipSuccess ? PTALM_OK : fail_hip(e, "coupling kernel launch");
+    if (wtmp) {
+        e = hipFreeAsync(wtmp, stream);
+        if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync");
+    }
+    return rc;
+}
+
+int ptalm_bandpower_count(int lmax, int lmin, int delta_l) {
+    if (!lmax_ok(lmax)) return 0;
+    return ptalm::bandpower_count(lmax, lmin, delta_l);
+}
+
+int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, int lmax_w, int lmax, int lmin,
+                     int delta_l, int mode, double *cb, double *window, void *stream_) {
+    g_error.clear();
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    const int nb = ptalm::bandpower_count(lmax, lmin, delta_l);
+    if (nb < 1) return fail(PTALM_EINVAL, "no complete bin: need 0 <= lmin <= lmax and delta_l >= 1 within lmax");
+    if (nb > 1024) return fail(PTALM_EINVAL, "more than 1024 bins");
+    if (mode != 0 && mode != 1) return fail(PTALM_EINVAL, "mode must be 0 (decoupled) or 1 (normalised)");
+    if (cl_hat == nullptr || M == nullptr || cb == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    if (mode == 1 && (Wl == nullptr || lmax_w < 0)) return fail(PTALM_EINVAL, "the normalised convention needs W_l");
+    hipStream_t stream = (hipStream_t)stream_;
+    double *scratch = nullptr;
+    hipError_t e = hipMallocAsync((void **)&scratch, sizeof(double) * ptalm::bandpower_scratch_doubles(lmax, nb), stream);
+    if (e != hipSuccess) return fail_hip(e, "hipMallocAsync");
+    e = ptalm::launch_bandpowers(cl_hat, M, Wl, lmax_w, lmax, lmin, delta_l, nb, mode, cb, window, scratch, stream);
+    int rc = e == hipSuccess ? PTALM_OK : fail_hip(e, "bandpower kernel launch");
+    e = hipFreeAsync(scratch, stream);
+    if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync");
+    return rc;
+}
+
 int ptalm_prepare(int lmax) {
     g_error.clear();
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");

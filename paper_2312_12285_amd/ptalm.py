@@ -58,6 +58,11 @@ _last_timing = _sig("ptalm_last_timing", ctypes.c_int, [ctypes.POINTER(ctypes.c_
 _release = _sig("ptalm_release_cache", ctypes.c_int, [])
 _prepare = _sig("ptalm_prepare", ctypes.c_int, [ctypes.c_int])
 _plan_ranges = _sig("ptalm_plan_m_ranges", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
+_shot = _sig("ptalm_window_shot_noise", ctypes.c_int, [_vp, _i64, _vp, _vp, _vp])
+_coupling = _sig("ptalm_coupling_matrix", ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp])
+_bp_count = _sig("ptalm_bandpower_count", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int])
+_bandpowers = _sig("ptalm_bandpowers", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                     ctypes.c_int, ctypes.c_int, _vp, _vp, _vp])
 _prepare_call = _sig("ptalm_prepare_call", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
 _autotune = _sig("ptalm_autotune", ctypes.c_int,
                  [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts), _vp])
@@ -218,6 +223,43 @@ def fkp_fields(alm_data, alm_randoms, lmax: int, stream=None):
 def prepare(lmax: int):
     """Build the per-lmax coefficient tables on the current device ahead of first use."""
     _check(_prepare(lmax))
+
+
+def window_shot_noise(w, alpha=None, out=None, stream=None):
+    """alpha^2 sum_i w_i^2 / (4 pi) (device scalar tensor); alpha a 1-element device tensor or None."""
+    _dev_f64(w, "w")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=w.device)
+    _check(_shot(_ptr(w), w.numel(), None if alpha is None else _ptr(alpha), _ptr(out), _stream(stream)))
+    return out
+
+
+def coupling_matrix(Wl, lmax: int, shot=None, out=None, stream=None):
+    """Mode-coupling matrix M[l, l'] (eq. chat) from the window spectrum Wl[0..lmax_w]; float64
+    [(lmax+1), (lmax+1)].  shot: optional 1-element device tensor subtracted from W first."""
+    _dev_f64(Wl, "Wl")
+    if out is None:
+        out = torch.empty((lmax + 1, lmax + 1), dtype=torch.float64, device=Wl.device)
+    _check(_coupling(_ptr(Wl), Wl.numel() - 1, None if shot is None else _ptr(shot), lmax, _ptr(out),
+                     _stream(stream)))
+    return out
+
+
+def bandpower_count(lmax: int, lmin: int, delta_l: int) -> int:
+    return int(_bp_count(lmax, lmin, delta_l))
+
+
+def bandpowers(cl_hat, M, lmax: int, delta_l: int, lmin: int = 0, mode: int = 0, Wl=None, stream=None):
+    """(cb, window): mode 0 mode-decoupled (eq. mode_coupling), 1 normalised."""
+    _dev_f64(cl_hat, "cl_hat"); _dev_f64(M, "M")
+    nb = bandpower_count(lmax, lmin, delta_l)
+    cb = torch.empty(max(nb, 1), dtype=torch.float64, device=M.device)
+    window = torch.empty((max(nb, 1), lmax + 1), dtype=torch.float64, device=M.device)
+    if Wl is not None:
+        _dev_f64(Wl, "Wl")
+    _check(_bandpowers(_ptr(cl_hat), _ptr(M), None if Wl is None else _ptr(Wl), -1 if Wl is None else Wl.numel() - 1,
+                       lmax, lmin, delta_l, mode, _ptr(cb), _ptr(window), _stream(stream)))
+    return cb, window
 
 
 def prepare_call(n: int, lmax: int, options: Opts | None = None):
