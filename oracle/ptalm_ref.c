@@ -378,22 +378,36 @@ double ptalm_ref_threej000(int l1, int l2, int l3)
     return (double)((h & 1) ? -v : v);
 }
 
+static double coupling_entry(const double *Wl, int lmax_w, int l, int lp)
+{
+    const long double inv4pi = 1.0L / (4.0L * 3.14159265358979323846264338327950288L);
+    long double sum = 0.0L;
+    const int lo = l > lp ? l - lp : lp - l;
+    const int hi = l + lp < lmax_w ? l + lp : lmax_w;
+    for (int lam = lo; lam <= hi; lam += 2) {
+        const long double t = (long double)ptalm_ref_threej000(l, lp, lam);
+        sum += (2.0L * lam + 1.0L) * t * t * (long double)Wl[lam];
+    }
+    return (double)((2.0L * lp + 1.0L) * inv4pi * sum);
+}
+
 int ptalm_ref_coupling_matrix(const double *Wl, int lmax_w, int lmax, double *M, int nthreads)
 {
     if (Wl == NULL || M == NULL || lmax < 0 || lmax_w < 0) return -1;
-    const long double inv4pi = 1.0L / (4.0L * 3.14159265358979323846264338327950288L);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
-    for (int l = 0; l <= lmax; ++l) {
-        for (int lp = 0; lp <= lmax; ++lp) {
-            long double sum = 0.0L;
-            const int lo = l > lp ? l - lp : lp - l;
-            const int hi = l + lp < lmax_w ? l + lp : lmax_w;
-            for (int lam = lo; lam <= hi; lam += 2) {
-                const long double t = (long double)ptalm_ref_threej000(l, lp, lam);
-                sum += (2.0L * lam + 1.0L) * t * t * (long double)Wl[lam];
-            }
-            M[(int64_t)l * (lmax + 1) + lp] = (double)((2.0L * lp + 1.0L) * inv4pi * sum);
-        }
-    }
+    for (int l = 0; l <= lmax; ++l)
+        for (int lp = 0; lp <= lmax; ++lp) M[(int64_t)l * (lmax + 1) + lp] = coupling_entry(Wl, lmax_w, l, lp);
+    return 0;
+}
+
+int ptalm_ref_coupling_rows(const double *Wl, int lmax_w, int lmax, const int *rows, int nrows, double *out,
+                            int nthreads)
+{
+    if (Wl == NULL || rows == NULL || out == NULL || lmax < 0 || lmax_w < 0 || nrows < 0) return -1;
+    for (int k = 0; k < nrows; ++k)
+        if (rows[k] < 0 || rows[k] > lmax) return -1;
+#pragma omp parallel for collapse(2) schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+    for (int k = 0; k < nrows; ++k)
+        for (int lp = 0; lp <= lmax; ++lp) out[(int64_t)k * (lmax + 1) + lp] = coupling_entry(Wl, lmax_w, rows[k], lp);
     return 0;
 }

@@ -66,6 +66,11 @@ double ptalm_ref_threej000(int l1, int l2, int l3);
  * parallel over l.  Returns 0, or -1 on bad arguments. */
 int ptalm_ref_coupling_matrix(const double *Wl, int lmax_w, int lmax, double *M, int nthreads);
 
+/* Rows of the same matrix: out[k][l'] = M[rows[k]][l'] for k < nrows, l' <= lmax
+ * (for sampled checks at sizes where the full matrix is too slow). */
+int ptalm_ref_coupling_rows(const double *Wl, int lmax_w, int lmax, const int *rows, int nrows, double *out,
+                            int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,8 +29,9 @@ def _bind(path):
     lib.ptalm_ref_threej000.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.ptalm_ref_threej000.restype = ctypes.c_double
     lib.ptalm_ref_coupling_matrix.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+    lib.ptalm_ref_coupling_rows.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _dp, ctypes.c_int]
     for f in ("ptalm_ref_alm_from_points", "ptalm_ref_alm_from_points_ld", "ptalm_ref_alm_entries",
-              "ptalm_ref_cl_from_alm", "ptalm_ref_cross_cl", "ptalm_ref_coupling_matrix"):
+              "ptalm_ref_cl_from_alm", "ptalm_ref_cross_cl", "ptalm_ref_coupling_matrix", "ptalm_ref_coupling_rows"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -159,6 +160,18 @@ def coupling_matrix(Wl, lmax: int, nthreads: int = 0) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return M
+
+
+def coupling_rows(Wl, lmax: int, rows, nthreads: int = 0) -> np.ndarray:
+    """Rows M[rows[k], 0..lmax] of the coupling matrix."""
+    Wl = _f64(Wl)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((rows.size, lmax + 1))
+    rc = _load().ptalm_ref_coupling_rows(_ptr(Wl), Wl.size - 1, lmax, rows.ctypes.data_as(_ip), rows.size,
+                                         _ptr(out), nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out
 
 
 def bin_matrix(lmax: int, delta_l: int, lmin: int = 0):

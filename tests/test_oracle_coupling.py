@@ -147,3 +147,13 @@ def test_bandpowers_recover_piecewise_constant_and_shot_noise(oracle):
     far = (np.arange(nb) + 1) * dl + lw <= lmax
     assert np.abs(cbn[far] - c0).max() < 1e-12 * c0
     assert np.all(window_n >= 0)
+
+
+def test_coupling_rows_match_full_matrix(oracle):
+    """The row sampler used for large-lmax checks returns rows of the same matrix."""
+    W = np.abs(np.random.default_rng(11).normal(size=91))
+    M = oracle.coupling_matrix(W, 60)
+    rows = [0, 1, 7, 33, 60]
+    assert np.array_equal(oracle.coupling_rows(W, 60, rows), M[rows])
+    with pytest.raises(ValueError):
+        oracle.coupling_rows(W, 60, [61])
