@@ -15,6 +15,11 @@ Workloads (--workload):
   multi2048    1e7 masked positions shared by 32 lognormal weight vectors, lmax 2048,
                split-bf16 MFMA form; tuned by the library's autotuner on a prefix,
                then each step replays one captured HIP graph (transform + 32 spectra)
+  coupling3072 mode coupling and bandpowers from a window spectrum W_l (l <= 6144) and a
+               pseudo-spectrum (l <= 3072): shot noise of 1e8 unit-weight randoms scaled by
+               alpha, M_ll' (l, l' <= 3072) with the shot noise removed from W, decoupled
+               and normalised bandpowers (delta_l 25 from l = 2); value = terms of the
+               coupling sum (l, l', lambda) per second
   served       a Poisson stream (50/s) of 500 masked catalogs, n log-uniform in
                [1e4, 1e7], lmax uniform in {128, ..., 2048}, through the library's
                request server; value = terms/s of the stream, with p50/p99 latency,
@@ -51,6 +56,8 @@ WORKLOADS = {
     "fullsky64": dict(desc="full-sky uniform n=1e4, unit weights, lmax=64", lmax=64),
     "served": dict(desc="Poisson stream 50/s of masked catalogs, n log-uniform [1e4, 1e7], lmax uniform in "
                         "{128,256,512,1024,2048}, lognormal sigma=0.3 weights, through the request server", lmax=2048),
+    "coupling3072": dict(desc="mode coupling lmax=3072 from W_l to 6144 (shot noise of n=1e8 unit-weight randoms "
+                              "removed), decoupled and normalised bandpowers delta_l=25 from l=2", lmax=3072),
     "multi2048": dict(desc="one masked position set n=1e7 shared by 32 lognormal weight vectors (sigma=0.2), "
                            "lmax=2048, split-bf16 MFMA form", lmax=2048),
 }
@@ -255,6 +262,111 @@ def run_multi(args, cats, lmax):
     print(json.dumps(line), flush=True)
 
 
+COUPLING_LW = 6144
+COUPLING_DL, COUPLING_LMIN = 25, 2
+COUPLING_RANDOMS = 100_000_000
+
+
+def coupling_terms(lmax, lmax_w, rows=None):
+    """Terms (l, l', lambda) of the coupling sum (eq. chat) over rows l (all if None) and all
+    l' <= lmax: lambda runs over |l - l'| .. min(l + l', lmax_w) in steps of 2."""
+    import numpy as np
+    ls = np.arange(lmax + 1) if rows is None else np.asarray(rows)
+    lp = np.arange(lmax + 1)
+    lo = np.abs(ls[:, None] - lp[None, :])
+    hi = np.minimum(ls[:, None] + lp[None, :], lmax_w)
+    return int(np.maximum((hi - lo) // 2 + 1, 0).sum())
+
+
+def run_coupling(args):
+    """coupling3072: shot noise, coupling matrix, both bandpower conventions per step."""
+    import numpy as np
+    import torch
+    from oracle import ref
+    from paper_2312_12285_amd import ptalm, synth
+    lmax, lw = WORKLOADS["coupling3072"]["lmax"], COUPLING_LW
+    n_r = int(COUPLING_RANDOMS * args.scale)
+    W = synth.window_spectrum(lw, seed=5)
+    cl = synth.pseudo_spectrum(lmax, seed=6)
+    Wd = torch.as_tensor(W).cuda()
+    cld = torch.as_tensor(cl).cuda()
+    wr = torch.ones(n_r, dtype=torch.float64, device="cuda")
+    alpha = torch.tensor([0.02], dtype=torch.float64, device="cuda")
+    shot = torch.empty(1, dtype=torch.float64, device="cuda")
+    M = torch.empty((lmax + 1, lmax + 1), dtype=torch.float64, device="cuda")
+    terms = coupling_terms(lmax, lw)
+    diag = sum(min(2 * l, lw) // 2 + 1 for l in range(lmax + 1))
+    half_terms = (terms + diag) // 2      # each unordered pair (l, l') once: the contraction's work
+    cms = []
+
+    def step():
+        ptalm.window_shot_noise(wr, alpha, out=shot)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ptalm.coupling_matrix(Wd, lmax, shot=shot, out=M)
+        b.record()
+        cms.append((a, b))
+        cb, win = ptalm.bandpowers(cld, M, lmax, COUPLING_DL, lmin=COUPLING_LMIN, mode=0)
+        cbn, winn = ptalm.bandpowers(cld, M, lmax, COUPLING_DL, lmin=COUPLING_LMIN, mode=1, Wl=Wd)
+        return cb, cbn
+
+    for i in range(args.warmup):
+        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
+        step()
+    torch.cuda.synchronize()
+    cms.clear()
+    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        cb, cbn = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in cms]))
+    flops = 2.0 * half_terms       # one multiply-add per term of the contraction, each unordered (l, l') once
+    achieved = flops / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "coupling_tables_kernel + coupling_mfma_kernel (one ptalm_coupling_matrix call)",
+                "kernel_ms_per_launch": round(k_ms, 4), "flops_per_term": 2,
+                "terms_per_launch": half_terms}
+    line = {"metric": "coupling-sum terms (l,l',lambda)/s, mode coupling + bandpowers", "value": terms * args.steps / elapsed,
+            "unit": "(l,l',lambda) terms/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": WORKLOADS["coupling3072"]["desc"], "lmax": lmax, "lmax_w": lw,
+                       "randoms": n_r, "delta_l": COUPLING_DL, "lmin": COUPLING_LMIN,
+                       "bins": ptalm.bandpower_count(lmax, COUPLING_LMIN, COUPLING_DL), "terms_per_step": terms},
+            "roofline": roofline}
+    if not args.no_check:
+        print("[bench] sampled rows of M against the oracle", file=sys.stderr, flush=True)
+        s = float(shot.cpu()[0])
+        want_shot = 0.02 ** 2 * n_r / (4 * math.pi)
+        rows = [0, 1, 1024, 2047, 3072]
+        t1 = time.time()
+        want = ref.coupling_rows(W - s, lmax, rows)
+        got = M.cpu().numpy()[rows]
+        line["parity"] = {"rows": rows, "max_rel_err": float((np.abs(got - want) / np.abs(want)).max()),
+                          "shot_rel_err": abs(s - want_shot) / want_shot, "oracle_seconds": round(time.time() - t1, 1)}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle coupling rows)", file=sys.stderr, flush=True)
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        rows = list(range(0, lmax + 1, 128))
+        t1 = time.time()
+        ref.coupling_rows(W, lmax, rows, nthreads=nthreads)
+        dt = time.time() - t1
+        k = coupling_terms(lmax, lw, rows)
+        if dt < args.cpu_seconds / 3:
+            rows = list(range(0, lmax + 1, 64))
+            t1 = time.time()
+            ref.coupling_rows(W, lmax, rows, nthreads=nthreads)
+            dt = time.time() - t1
+            k = coupling_terms(lmax, lw, rows)
+        line["cpu_baseline"] = {"value": k / dt, "unit": "(l,l',lambda) terms/s", "cores": nthreads, "kind": "oracle",
+                                "sample": f"{len(rows)} rows of M (every {rows[1] - rows[0]}th l) at lmax {lmax}, "
+                                          f"{k:.3g} terms, {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def _served_catalogs(reqs, workers):
     """Host generation of every request's catalog in a fork pool (before the GPU is touched)."""
     import concurrent.futures as cf
@@ -396,6 +508,8 @@ def main():
     if args.workload == "served":        # generates its catalogs in worker processes before touching the GPU
         return run_served(args)
 
+    if args.workload == "coupling3072":
+        return run_coupling(args)
     import numpy as np
     import torch
     from paper_2312_12285_amd import ptalm

@@ -156,7 +156,9 @@ int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax
 
 /* Shot noise of a weighted point set: out[0] = a^2 sum_i w_i^2 / (4 pi) with
  * a = alpha[0] (device) or 1 if alpha is NULL; for the window of scaled
- * randoms (the footnote to eq. wldef).  Fixed summation order. */
+ * randoms (the footnote to eq. wldef).  Fixed summation order (per-block
+ * partial sums, then their sum in block order).  Allocates stream-ordered
+ * scratch. */
 int ptalm_window_shot_noise(const double *w, int64_t n, const double *alpha, double *out, void *stream);
 
 /* Mode-coupling matrix
@@ -165,8 +167,11 @@ int ptalm_window_shot_noise(const double *w, int64_t n, const double *alpha, dou
  *           counts as 0; W up to 2 lmax gives the complete matrix);
  *   shot  : NULL, or one device double subtracted from every W_lambda first;
  *   M     : (lmax+1)^2 doubles, row-major in l (output).
- * FP64, one thread per (l, l'); the 3j squares come from the recurrences of
- * App. C without square roots.  PTALM_EINVAL on bad sizes or NULL pointers. */
+ * FP64.  With J = (l + l' + lambda)/2 and a(n) = binom(2n, n)/4^n the 3j square
+ * is a(J-l) a(J-l') a(J-lambda) / ((2J+1) a(J)); the matrix is computed as a
+ * triangular matrix product on the matrix cores from tables of a(n) (the same
+ * values the App. C recurrence gives).  Allocates stream-ordered scratch.
+ * PTALM_EINVAL on bad sizes or NULL pointers. */
 int ptalm_coupling_matrix(const double *Wl, int lmax_w, const double *shot, int lmax, double *M, void *stream);
 
 /* Number of complete bins [lmin + b delta_l, lmin + (b+1) delta_l) within lmax (0 if none). Host only. */
@@ -176,9 +181,9 @@ int ptalm_bandpower_count(int lmax, int lmin, int delta_l);
  * those bins (Sec. 2.1):
  *   mode 0, mode-decoupled (eq. mode_coupling): cb = Mbb^-1 theta cl_hat with
  *     Mbb[b][b'] = sum_{l in b} sum_{l' in b'} theta_b^l M[l][l'], and
- *     window = Mbb^-1 theta M (eq. expectation_value), by Gauss-Jordan
- *     elimination with partial pivoting in FP64 (a singular Mbb, from bins too
- *     narrow for the mask, gives non-finite output);
+ *     window = Mbb^-1 theta M (eq. expectation_value), by LU factorisation of
+ *     Mbb with partial pivoting and forward/back substitution in FP64 (a
+ *     singular Mbb, from bins too narrow for the mask, gives non-finite output);
  *   mode 1, normalised: cb = N theta cl_hat, window = N theta M with
  *     1/N = sum_l (2l+1) W_l / (4 pi) (needs Wl, lmax_w).
  * cb: nb doubles, window: nb x (lmax+1) doubles row-major (may be NULL).

@@ -432,8 +432,15 @@ int ptalm_window_shot_noise(const double *w, int64_t n, const double *alpha, dou
     g_error.clear();
     if (n < 0) return fail(PTALM_EINVAL, "n < 0");
     if (out == nullptr || (n > 0 && w == nullptr)) return fail(PTALM_EINVAL, "NULL pointer");
-    hipError_t e = ptalm::launch_shot_noise(w, n, alpha, out, (hipStream_t)stream);
-    return e == hipSuccess ? PTALM_OK : fail_hip(e, "shot-noise kernel launch");
+    hipStream_t st = (hipStream_t)stream;
+    double *partial = nullptr;
+    hipError_t e = hipMallocAsync((void **)&partial, sizeof(double) * ptalm::shot_noise_scratch_doubles(), st);
+    if (e != hipSuccess) return fail_hip(e, "hipMallocAsync");
+    e = ptalm::launch_shot_noise(w, n, alpha, out, partial, st);
+    int rc = e == hipSuccess ? PTALM_OK : fail_hip(e, "shot-noise kernel launch");
+    e = hipFreeAsync(partial, st);
+    if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync");
+    return rc;
 }
 
 int ptalm_coupling_matrix(const double *Wl, int lmax_w, const double *shot, int lmax, double *M, void *stream_) {
@@ -441,16 +448,13 @@ int ptalm_coupling_matrix(const double *Wl, int lmax_w, const double *shot, int 
     if (!lmax_ok(lmax) || lmax_w < 0 || lmax_w > 2 * PTALM_LMAX_MAX + 1) return fail(PTALM_EINVAL, "lmax out of range");
     if (Wl == nullptr || M == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
     hipStream_t stream = (hipStream_t)stream_;
-    double *wtmp = nullptr;
-    hipError_t e;
-    if (shot != nullptr && (e = hipMallocAsync((void **)&wtmp, sizeof(double) * (lmax_w + 1), stream)) != hipSuccess)
-        return fail_hip(e, "hipMallocAsync");
-    e = ptalm::launch_coupling(Wl, lmax_w, shot, wtmp, lmax, M, stream);
+    double *scratch = nullptr;
+    hipError_t e = hipMallocAsync((void **)&scratch, sizeof(double) * ptalm::coupling_scratch_doubles(lmax), stream);
+    if (e != hipSuccess) return fail_hip(e, "hipMallocAsync");
+    e = ptalm::launch_coupling(Wl, lmax_w, shot, scratch, lmax, M, stream);
     int rc = e == hipSuccess ? PTALM_OK : fail_hip(e, "coupling kernel launch");
-    if (wtmp) {
-        e = hipFreeAsync(wtmp, stream);
-        if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync");
-    }
+    e = hipFreeAsync(scratch, stream);
+    if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync");
     return rc;
 }
 

@@ -120,12 +120,15 @@ bool fp32_variant_exists(int kp, int lb, int mode);
 // mode coupling and bandpowers (coupling.hip)
 int bandpower_count(int lmax, int lmin, int delta_l);
 size_t bandpower_scratch_doubles(int lmax, int nb);
-hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, double *wtmp, int lmax, double *M,
+size_t coupling_scratch_doubles(int lmax);
+hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, double *scratch, int lmax, double *M,
                            hipStream_t stream);
 hipError_t launch_bandpowers(const double *cl_hat, const double *M, const double *Wl, int lmax_w, int lmax, int lmin,
                              int delta_l, int nb, int mode, double *cb, double *window, double *scratch,
                              hipStream_t stream);
-hipError_t launch_shot_noise(const double *w, int64_t n, const double *alpha, double *out, hipStream_t stream);
+size_t shot_noise_scratch_doubles();
+hipError_t launch_shot_noise(const double *w, int64_t n, const double *alpha, double *out, double *partial,
+                             hipStream_t stream);
 
 bool multi_nw_supported(int nw);
 hipError_t launch_alm_multi(const MultiArgs &a, hipStream_t stream);

@@ -214,3 +214,27 @@ def served_trace(k: int = 500, rate_hz: float = 50.0, seed: int = 51,
 def served_catalog(req: Request, sigma: float = 0.3) -> Catalog:
     t, p = uniform_in_mask(req.n, req.seed)
     return Catalog(t, p, lognormal_weights(req.n, sigma, req.seed + 1_000_000))
+
+
+def window_spectrum(lmax_w: int, seed: int, f_sky: float = 0.344, slope: float = 2.5):
+    """Stand-in for the angular power spectrum of a survey window (mode-coupling workload):
+    4 pi f_sky^2 at l = 0, then 0.3 * 4 pi f_sky^2 (1 + l)^-slope, each l scaled by an
+    independent chi-square draw with 2(2l+1) degrees of freedom over its mean (the scatter of
+    a power estimated from 2l+1 complex modes), plus a floor of 1e-9 of W_0.  All positive."""
+    rng = np.random.default_rng(seed)
+    l = np.arange(lmax_w + 1, dtype=np.float64)
+    w0 = 4.0 * math.pi * f_sky * f_sky
+    dof = 2.0 * (2.0 * l + 1.0)
+    W = 0.3 * w0 * (1.0 + l) ** -slope * rng.chisquare(dof) / dof + 1e-9 * w0
+    W[0] = w0
+    return W
+
+
+def pseudo_spectrum(lmax: int, seed: int, amp: float = 1e-4, slope: float = 1.2, shot: float = 2e-6):
+    """Stand-in for a measured pseudo-spectrum of galaxy counts (bandpower workload):
+    amp (1 + l/10)^-slope scaled per l by a chi-square draw with 2l+1 degrees of freedom over
+    its mean, plus a constant shot-noise level."""
+    rng = np.random.default_rng(seed)
+    l = np.arange(lmax + 1, dtype=np.float64)
+    dof = 2.0 * l + 1.0
+    return amp * (1.0 + l / 10.0) ** -slope * rng.chisquare(dof) / dof + shot

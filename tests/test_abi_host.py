@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "ptalm.h")
 def lib():
     if not os.path.exists(LIB):
         pytest.fail("libptalm.so is not built (run __graft_entry__.build())")
-    return ctypes.CDLL(LIB)
+    return ctypes.CDLL(LIB, mode=os.RTLD_NOW | os.RTLD_LOCAL)   # every symbol resolved at load
 
 
 def declared_functions():

@@ -134,3 +134,56 @@ def test_two_catalog_path_to_bandpowers(lib, oracle):
     errn = np.abs(host(cbn) - cbn_ref).max() / np.abs(cbn_ref).max()
     print(f"two-catalog bandpowers: decoupled {errd:.2e}, normalised {errn:.2e}", flush=True)
     assert errd <= 1e-8 and errn <= 1e-9
+
+
+@pytest.mark.parametrize("lmax,dl,lmin", [(0, 1, 0), (126, 1, 0), (127, 1, 0), (128, 1, 0), (150, 1, 11), (139, 1, 0), (140, 1, 0), (299, 1, 0),
+                                          (1023, 1, 0), (700, 3, 5)])
+def test_bandpower_solve_sizes(lib, oracle, lmax, dl, lmin):
+    """The decoupling solve at bin counts on both sides of the in-register (128) and in-LDS (140)
+    factorisation limits and
+    at the 1024-bin maximum, on a well-conditioned synthetic coupling matrix."""
+    rng = np.random.default_rng(lmax + dl)
+    n1 = lmax + 1
+    Mh = np.eye(n1) * (1.0 + rng.random(n1)) + rng.random((n1, n1)) * (0.5 / n1)
+    cl_hat = 1.0 + rng.random(n1)
+    theta, chi = oracle.bin_matrix(lmax, dl, lmin)
+    print(f"bandpower solve lmax {lmax} delta_l {dl} lmin {lmin}: nb {theta.shape[0]}", flush=True)
+    cb, window = lib.bandpowers(dev(cl_hat), dev(Mh), lmax, dl, lmin=lmin, mode=0)
+    cb_ref, win_ref, _ = oracle.decoupled_bandpowers(cl_hat, Mh, theta, chi)
+    assert np.abs(host(cb) - cb_ref).max() <= 1e-12 * np.abs(cb_ref).max()
+    assert np.abs(host(window) - win_ref).max() <= 1e-12 * np.abs(win_ref).max()
+
+
+def test_coupling_and_bandpowers_full_size(lib, oracle):
+    """Full size of the coupling workload (lmax 3072 from W_l to 6144): sampled rows of M
+    against the oracle row by row (every tile column, the diagonal block, both parities,
+    the last rows), and both bandpower conventions against the oracle's bandpower algebra
+    applied to the same M."""
+    import torch
+    from paper_2312_12285_amd.synth import window_spectrum
+    lmax, lw, dl = 3072, 6144, 25
+    W = window_spectrum(lw, seed=5)
+    Wd = dev(W)
+    M = lib.coupling_matrix(Wd, lmax)
+    rows = [0, 1, 2, 63, 64, 65, 1000, 2047, 3071, 3072]
+    Mh = host(M)
+    ref = oracle.coupling_rows(W, lmax, rows)
+    rel = np.abs(Mh[rows] - ref) / np.abs(ref)
+    print(f"coupling lmax {lmax}: sampled-row max rel err {rel.max():.3e}", flush=True)
+    assert rel.max() <= 1e-12
+    # the transpose relation of the definition: (2l+1) M[l][l'] = (2l'+1) M[l'][l]
+    l = np.arange(lmax + 1.0)
+    sym = (2 * l[:, None] + 1) * Mh
+    assert np.abs(sym - sym.T).max() <= 1e-13 * np.abs(sym).max()
+    rng = np.random.default_rng(6)
+    cl_hat = Mh @ (1.0 + 30.0 / (l + 10.0)) + 1e-3 * rng.random(lmax + 1)
+    theta, chi = oracle.bin_matrix(lmax, dl, 2)
+    cb, win = lib.bandpowers(dev(cl_hat), M, lmax, dl, lmin=2, mode=0)
+    cbn, winn = lib.bandpowers(dev(cl_hat), M, lmax, dl, lmin=2, mode=1, Wl=Wd)
+    torch.cuda.synchronize()
+    cb_ref, win_ref, _ = oracle.decoupled_bandpowers(cl_hat, Mh, theta, chi)
+    cbn_ref, winn_ref, _ = oracle.normalized_bandpowers(cl_hat, Mh, theta, W)
+    assert np.abs(host(cb) - cb_ref).max() <= 1e-9 * np.abs(cb_ref).max()
+    assert np.abs(host(win) - win_ref).max() <= 1e-9 * np.abs(win_ref).max()
+    assert np.abs(host(cbn) - cbn_ref).max() <= 1e-12 * np.abs(cbn_ref).max()
+    assert np.abs(host(winn) - winn_ref).max() <= 1e-12 * np.abs(winn_ref).max()
