@@ -192,6 +192,33 @@ int ptalm_bandpower_count(int lmax, int lmin, int delta_l);
 int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, int lmax_w, int lmax, int lmin,
                      int delta_l, int mode, double *cb, double *window, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Interpolated transform (App. A.2): cubic Hermite splines of y_lm(x) and
+ * y'_lm(x) on a node grid instead of the per-point recurrence.
+ * ------------------------------------------------------------------------ */
+
+#define PTALM_SPLINE_NODES_MAX 65536
+
+/* a_lm ~= sum_i w_i Y*_lm(theta_i, phi_i) by the interpolated transform of
+ * App. A.2, same arguments and output layout as ptalm_alm_from_points:
+ *   n_nodes   : spline nodes, uniform in theta over [theta_cut, pi - theta_cut]
+ *               (x_j = cos(pi - theta_cut - j h), ascending in x);
+ *   theta_cut : points with theta < theta_cut or theta > pi - theta_cut (the
+ *               polar caps) take the exact sum instead of the spline; in (0, pi/2).
+ * Per interval [x_j, x_{j+1}) and order m the points are summed into the
+ * binned weights v_ja^(m) = sum w e^{-i m phi} c_a(t) (the Hermite basis of
+ * App. A.2, with the (x_{j+1} - x_j) factors on the derivative terms), and
+ * a_lm = sum_j [v_j0 y(x_j) + v_j1 dx_j y'(x_j) + v_j2 y(x_{j+1}) + v_j3 dx_j y'(x_{j+1})]
+ * with y' from the derivative relation of App. A.1.  Approximate: the error
+ * falls like (l h)^4 with the node spacing h in theta.  FP64 throughout.
+ * Allocates stream-ordered scratch (about 40 B per point plus
+ * (lmax+1) x n_nodes x 112 B) and synchronizes `stream` once (to size the
+ * polar part).  Points inside one interval are summed in the order a scatter
+ * with atomic counters placed them, so repeated calls can differ in the last
+ * bits.  PTALM_EINVAL on bad sizes or pointers. */
+int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
+                                 int n_nodes, double theta_cut, double *alm, void *stream);
+
 /* Device time of the transform kernel(s) of the last ptalm_alm_from_points_ex
  * call made on this thread with opts->timing set: from just before the first
  * transform kernel to just after the last one, on that call's stream.  Blocks

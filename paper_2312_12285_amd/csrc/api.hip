@@ -484,6 +484,96 @@ int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, in
     return rc;
 }
 
+namespace {
+
+// stream-ordered allocations released together (in reverse order) at scope end
+struct AsyncAllocs {
+    hipStream_t stream;
+    std::vector<void *> ptrs;
+    explicit AsyncAllocs(hipStream_t s) : stream(s) {}
+    hipError_t get(void **p, size_t bytes) {
+        *p = nullptr;
+        hipError_t e = hipMallocAsync(p, bytes < 256 ? 256 : bytes, stream);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    hipError_t release() {
+        hipError_t first = hipSuccess;
+        for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it) {
+            hipError_t e = hipFreeAsync(*it, stream);
+            if (first == hipSuccess) first = e;
+        }
+        ptrs.clear();
+        return first;
+    }
+    ~AsyncAllocs() { release(); }
+};
+
+}  // namespace
+
+int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
+                                 int n_nodes, double theta_cut, double *alm, void *stream_) {
+    g_error.clear();
+    if (n < 0) return fail(PTALM_EINVAL, "n < 0");
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (alm == nullptr || (n > 0 && (theta == nullptr || phi == nullptr || w == nullptr)))
+        return fail(PTALM_EINVAL, "NULL pointer");
+    if (n_nodes < 2 || n_nodes > PTALM_SPLINE_NODES_MAX) return fail(PTALM_EINVAL, "n_nodes out of range");
+    const double kPi = 3.141592653589793;
+    if (!(theta_cut > 0.0 && theta_cut < 0.5 * kPi)) return fail(PTALM_EINVAL, "theta_cut must be in (0, pi/2)");
+    hipStream_t stream = (hipStream_t)stream_;
+    const double h = (kPi - 2.0 * theta_cut) / (n_nodes - 1);
+    const int64_t T = ptalm::tri_size(lmax);
+    AsyncAllocs mem(stream);
+    double *xn, *thn;
+    unsigned *counts, *cursors;
+    int64_t *offsets;
+    hipError_t e;
+    if ((e = mem.get((void **)&xn, sizeof(double) * n_nodes)) != hipSuccess ||
+        (e = mem.get((void **)&thn, sizeof(double) * n_nodes)) != hipSuccess ||
+        (e = mem.get((void **)&counts, sizeof(unsigned) * n_nodes)) != hipSuccess ||
+        (e = mem.get((void **)&cursors, sizeof(unsigned) * n_nodes)) != hipSuccess ||
+        (e = mem.get((void **)&offsets, sizeof(int64_t) * (n_nodes + 1))) != hipSuccess)
+        return fail_hip(e, "hipMallocAsync");
+    if ((e = ptalm::launch_spline_count(theta, n, theta_cut, h, n_nodes, xn, thn, counts, stream)) != hipSuccess)
+        return fail_hip(e, "spline count kernels");
+    // the polar count sizes the arrays below: one synchronisation
+    unsigned n_polar_u = 0;
+    if ((e = hipMemcpyAsync(&n_polar_u, counts + (n_nodes - 1), sizeof(unsigned), hipMemcpyDeviceToHost, stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return fail_hip(e, "reading the polar count");
+    const int64_t n_polar = n_polar_u, n_spline = n - n_polar;
+    double *q, *pth, *pph, *pw;
+    if ((e = mem.get((void **)&q, sizeof(double) * 5 * (size_t)n_spline)) != hipSuccess ||
+        (e = mem.get((void **)&pth, sizeof(double) * (size_t)n_polar)) != hipSuccess ||
+        (e = mem.get((void **)&pph, sizeof(double) * (size_t)n_polar)) != hipSuccess ||
+        (e = mem.get((void **)&pw, sizeof(double) * (size_t)n_polar)) != hipSuccess)
+        return fail_hip(e, "hipMallocAsync");
+    if ((e = ptalm::launch_spline_scatter(theta, phi, w, n, theta_cut, h, n_nodes, xn, counts, offsets, cursors, q,
+                                          n_spline, pth, pph, pw, stream)) != hipSuccess)
+        return fail_hip(e, "spline scatter kernels");
+    const ptalm::SplinePlan plan = ptalm::spline_plan(n, lmax, n_nodes);
+    double *v, *wn, *state;
+    if ((e = mem.get((void **)&v, sizeof(double) * plan.v_doubles)) != hipSuccess ||
+        (e = mem.get((void **)&wn, sizeof(double) * plan.wn_doubles)) != hipSuccess ||
+        (e = mem.get((void **)&state, sizeof(double) * plan.state_doubles)) != hipSuccess)
+        return fail_hip(e, "hipMallocAsync");
+    if ((e = ptalm::launch_spline_transform(plan, q, n_spline, offsets, xn, thn, n_nodes, lmax, (double2 *)v,
+                                            (double2 *)wn, state, alm, stream)) != hipSuccess)
+        return fail_hip(e, "spline transform kernels");
+    if (n_polar > 0) {   // the polar caps by the exact sum, added to the interpolated part
+        double *tmp;
+        if ((e = mem.get((void **)&tmp, sizeof(double) * 2 * (size_t)T)) != hipSuccess)
+            return fail_hip(e, "hipMallocAsync");
+        const int rc = ptalm_alm_from_points_ex(pth, pph, pw, n_polar, lmax, tmp, nullptr, nullptr, 0, stream);
+        if (rc != PTALM_OK) return rc;
+        if ((e = ptalm::launch_axpy(1.0, tmp, alm, 2 * T, stream)) != hipSuccess) return fail_hip(e, "axpy");
+    }
+    if ((e = mem.release()) != hipSuccess) return fail_hip(e, "hipFreeAsync");
+    return PTALM_OK;
+}
+
 int ptalm_prepare(int lmax) {
     g_error.clear();
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");

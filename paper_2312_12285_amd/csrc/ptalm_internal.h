@@ -130,6 +130,22 @@ size_t shot_noise_scratch_doubles();
 hipError_t launch_shot_noise(const double *w, int64_t n, const double *alpha, double *out, double *partial,
                              hipStream_t stream);
 
+// interpolated transform (spline.hip)
+struct SplinePlan {
+    int n_int = 0, n_pass = 0, n_chunks = 0;
+    size_t v_doubles = 0, wn_doubles = 0, state_doubles = 0;
+};
+SplinePlan spline_plan(int64_t n, int lmax, int n_nodes);
+hipError_t launch_spline_count(const double *theta, int64_t n, double theta_cut, double h, int n_nodes, double *xn,
+                               double *thn, unsigned *counts, hipStream_t stream);
+hipError_t launch_spline_scatter(const double *theta, const double *phi, const double *w, int64_t n, double theta_cut,
+                                 double h, int n_nodes, const double *xn, const unsigned *counts, int64_t *offsets,
+                                 unsigned *cursors, double *q, int64_t n_spline, double *pth, double *pph, double *pw,
+                                 hipStream_t stream);
+hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
+                                   const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
+                                   double2 *wn, double *state, double *alm, hipStream_t stream);
+
 bool multi_nw_supported(int nw);
 hipError_t launch_alm_multi(const MultiArgs &a, hipStream_t stream);
 hipError_t launch_multi_finish(const MultiArgs &a, const double *sigma, double *alm, hipStream_t stream);

@@ -1,0 +1,448 @@
+// Interpolated transform of App. A.2: cubic Hermite splines of y_lm(x) and
+// y'_lm(x) on a node grid, the points summed into per-m binned weights per
+// interval, and a sum over the nodes.  Points outside the spline region take
+// the exact direct sum (the caller adds it).
+//
+// Nodes: n_nodes nodes uniform in theta over [theta_cut, pi - theta_cut],
+// x_j = cos(pi - theta_cut - j h), ascending in x, h = (pi - 2 theta_cut)/(n_nodes - 1);
+// interval j = [x_j, x_{j+1}).  With t = (x - x_j)/(x_{j+1} - x_j) and the basis
+// c_0..c_3 of App. A.2,
+//   v_ja^(m) = sum_{r in j} w_r e^{-i m phi_r} c_a(t_r),
+//   a_lm = sum_j [v_j0 y(x_j) + v_j1 dx_j y'(x_j) + v_j2 y(x_{j+1}) + v_j3 dx_j y'(x_{j+1})],
+// which per node n is a_lm = sum_n V_n y_lm(x_n) + D_n y'_lm(x_n) with
+// V_n = v_n0 + v_{n-1,2}, D_n = dx_n v_n1 + dx_{n-1} v_{n-1,3}.  The derivative
+// relation of App. A.1, for the orthonormal functions,
+//   (1 - x^2) y'_l = -l x y_l + d_l y_{l-1},  d_l = sqrt((2l+1)/(2l-1) (l^2 - m^2)),
+// turns the derivative part into two more plain sums over the nodes:
+//   a_lm = A_l - l F_l + d_l G_{l-1},   A_l = sum_n V_n y_l(x_n),
+//   F_l = sum_n D_n x_n/(1-x_n^2) y_l(x_n),  G_l = sum_n D_n/(1-x_n^2) y_l(x_n).
+//
+// Steps: count points per interval (polar points in an extra bucket), scan,
+// scatter into interval order with the spline weights w c_a precomputed,
+// binning (one workgroup per (interval, 16 orders)), node weights per (m, n),
+// and the node sum (one workgroup per m: the recurrence over l for 256 nodes
+// at a time writes a tile of y_l(x_n) to LDS, then threads own an l each and
+// sum over the nodes of the tile, so no cross-lane reduction is needed).
+#include "ptalm_internal.h"
+
+namespace ptalm {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+
+__device__ inline int interval_of(double th, double theta_cut, double h, int n_int) {
+    if (th < theta_cut || th > kPi - theta_cut) return n_int;   // polar bucket
+    const double u = (kPi - theta_cut - th) / h;
+    const int j = (int)floor(u);
+    return j < n_int - 1 ? j : n_int - 1;
+}
+
+__global__ void zero_u32_kernel(unsigned *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+
+__global__ void nodes_kernel(double theta_cut, double h, int n_nodes, double *__restrict__ xn,
+                             double *__restrict__ thn) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_nodes) return;
+    const double th = kPi - theta_cut - h * j;
+    thn[j] = th;
+    xn[j] = cos(th);
+}
+
+__global__ void count_kernel(const double *__restrict__ theta, int64_t n, double theta_cut, double h, int n_int,
+                             unsigned *__restrict__ counts) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&counts[interval_of(theta[i], theta_cut, h, n_int)], 1u);
+}
+
+// offsets[b] = sum_{b' < b} counts[b'] for b <= nb (nb buckets), one workgroup;
+// cursors reset to 0
+__global__ __launch_bounds__(1024) void scan_kernel(const unsigned *__restrict__ counts, int nb,
+                                                    int64_t *__restrict__ offsets, unsigned *__restrict__ cursors) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int chunk = (nb + 1023) / 1024;
+    const int lo = tid * chunk < nb ? tid * chunk : nb;
+    const int hi = lo + chunk < nb ? lo + chunk : nb;
+    int64_t s = 0;
+    for (int b = lo; b < hi; ++b) s += counts[b];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[tid];
+    for (int b = lo; b < hi; ++b) {
+        offsets[b] = run;
+        run += counts[b];
+        cursors[b] = 0u;
+    }
+    if (tid == 1023) offsets[nb] = run;
+}
+
+// Points of the spline region in interval order with q_a = w c_a(t) and the
+// phase; polar points (bucket n_int) to their own arrays.  The order inside an
+// interval is the order of the atomic increments.
+__global__ void scatter_kernel(const double *__restrict__ theta, const double *__restrict__ phi,
+                               const double *__restrict__ w, int64_t n, double theta_cut, double h, int n_int,
+                               const double *__restrict__ xn, const int64_t *__restrict__ offsets,
+                               unsigned *__restrict__ cursors, double *__restrict__ q, int64_t n_spline,
+                               double *__restrict__ pth, double *__restrict__ pph, double *__restrict__ pw) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double th = theta[i], ph = phi[i], wi = w[i];
+        const int j = interval_of(th, theta_cut, h, n_int);
+        const int64_t pos = offsets[j] + atomicAdd(&cursors[j], 1u);
+        if (j == n_int) {
+            const int64_t p = pos - offsets[n_int];
+            pth[p] = th;
+            pph[p] = ph;
+            pw[p] = wi;
+            continue;
+        }
+        const double x = cos(th);
+        const double t = (x - xn[j]) / (xn[j + 1] - xn[j]);
+        const double u = 1.0 - t;
+        q[pos] = wi * ((2.0 * t + 1.0) * u * u);
+        q[n_spline + pos] = wi * (t * u * u);
+        q[2 * n_spline + pos] = wi * (t * t * (3.0 - 2.0 * t));
+        q[3 * n_spline + pos] = wi * (t * t * (t - 1.0));
+        q[4 * n_spline + pos] = ph;
+    }
+}
+
+constexpr int kBinM = 16;        // orders per binning workgroup
+constexpr int kBinThreads = 256;
+
+// v[((m n_int) + j) * 4 + a] (complex) for the orders [16 p, 16 p + 16) of interval j.
+// Workgroups are numbered so that consecutive ones (the passes over the same
+// interval) land on the same XCD and reuse its L2 copy of the interval's points.
+__global__ __launch_bounds__(kBinThreads) void bin_kernel(const double *__restrict__ q, int64_t n_spline,
+                                                          const int64_t *__restrict__ offsets, int n_int, int lmax,
+                                                          int n_pass, int64_t units_per_xcd,
+                                                          double2 *__restrict__ v) {
+    __shared__ double red[kBinThreads][33];
+    __shared__ double red2[8][32];
+    const int64_t L = (int64_t)(blockIdx.x & 7) * units_per_xcd + (blockIdx.x >> 3);
+    const int j = (int)(L / n_pass), pass = (int)(L % n_pass);
+    if (j >= n_int) return;
+    const int m0 = pass * kBinM;
+    const int tid = threadIdx.x;
+    double acc[kBinM][8];
+#pragma unroll
+    for (int mm = 0; mm < kBinM; ++mm)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[mm][c] = 0.0;
+    const int64_t lo = offsets[j], hi = offsets[j + 1];
+    for (int64_t r = lo + tid; r < hi; r += kBinThreads) {
+        const double q0 = q[r], q1 = q[n_spline + r], q2 = q[2 * n_spline + r], q3 = q[3 * n_spline + r];
+        const double ph = q[4 * n_spline + r];
+        double s1, c1, sm, cm;
+        sincos(ph, &s1, &c1);
+        sincos((double)m0 * ph, &sm, &cm);
+        double zr = cm, zi = -sm;          // e^{-i m phi}
+        const double ur = c1, ui = -s1;    // e^{-i phi}
+#pragma unroll
+        for (int mm = 0; mm < kBinM; ++mm) {
+            acc[mm][0] = fma(q0, zr, acc[mm][0]);
+            acc[mm][1] = fma(q0, zi, acc[mm][1]);
+            acc[mm][2] = fma(q1, zr, acc[mm][2]);
+            acc[mm][3] = fma(q1, zi, acc[mm][3]);
+            acc[mm][4] = fma(q2, zr, acc[mm][4]);
+            acc[mm][5] = fma(q2, zi, acc[mm][5]);
+            acc[mm][6] = fma(q3, zr, acc[mm][6]);
+            acc[mm][7] = fma(q3, zi, acc[mm][7]);
+            const double nr = zr * ur - zi * ui;
+            zi = fma(zr, ui, zi * ur);
+            zr = nr;
+        }
+    }
+    // sum over the workgroup in fixed order, 32 values per round through LDS
+#pragma unroll
+    for (int round = 0; round < kBinM * 8 / 32; ++round) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) red[tid][c] = acc[(round * 32 + c) / 8][(round * 32 + c) % 8];
+        __syncthreads();
+        {
+            const int vi = tid & 31, g = tid >> 5;
+            double s = 0.0;
+            for (int k = 0; k < 32; ++k) s += red[32 * g + k][vi];
+            red2[g][vi] = s;
+        }
+        __syncthreads();
+        if (tid < 32) {
+            double s = 0.0;
+            for (int g = 0; g < 8; ++g) s += red2[g][tid];
+            const int flat = round * 32 + tid;
+            const int mm = flat / 8, c = flat % 8;
+            const int m = m0 + mm;
+            if (m <= lmax) {
+                double *dst = (double *)(v + ((int64_t)m * n_int + j) * 4 + c / 2);
+                dst[c & 1] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Node weights per (m, n): V_n, F_n = D_n x_n/(1-x_n^2), G_n = D_n/(1-x_n^2) (complex),
+// wn[((m n_nodes) + n) * 3 + k]
+__global__ void node_weights_kernel(const double2 *__restrict__ v, const double *__restrict__ xn, int n_nodes,
+                                    int lmax, double2 *__restrict__ wn) {
+    const int64_t total = (int64_t)(lmax + 1) * n_nodes;
+    const int n_int = n_nodes - 1;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int m = (int)(e / n_nodes), n = (int)(e % n_nodes);
+        double vr = 0.0, vi = 0.0, dr = 0.0, di = 0.0;
+        if (n < n_int) {
+            const double2 a0 = v[((int64_t)m * n_int + n) * 4 + 0];
+            const double2 a1 = v[((int64_t)m * n_int + n) * 4 + 1];
+            const double dx = xn[n + 1] - xn[n];
+            vr += a0.x;
+            vi += a0.y;
+            dr += dx * a1.x;
+            di += dx * a1.y;
+        }
+        if (n > 0) {
+            const double2 a2 = v[((int64_t)m * n_int + n - 1) * 4 + 2];
+            const double2 a3 = v[((int64_t)m * n_int + n - 1) * 4 + 3];
+            const double dx = xn[n] - xn[n - 1];
+            vr += a2.x;
+            vi += a2.y;
+            dr += dx * a3.x;
+            di += dx * a3.y;
+        }
+        const double x = xn[n];
+        const double inv = 1.0 / (1.0 - x * x);
+        wn[e * 3 + 0] = make_double2(vr, vi);
+        wn[e * 3 + 1] = make_double2(dr * x * inv, di * x * inv);
+        wn[e * 3 + 2] = make_double2(dr * inv, di * inv);
+    }
+}
+
+constexpr int kNodeChunk = 256;   // nodes per tile (one per thread in the recurrence phase)
+constexpr int kNodeLB = 32;       // degrees per tile
+constexpr int kTilePitch = kNodeChunk + 1;
+
+// exact 2^e for the range used here, 0 below the double range
+__device__ inline double pow2i(int e) { return e < -1074 ? 0.0 : ldexp(1.0, e); }
+
+// One workgroup per order m.  Per block of 32 degrees and per chunk of 256
+// nodes: each thread advances its node's recurrence (state kept in global
+// scratch between blocks, as a scaled pair with a binary exponent) and writes
+// y_l(x_n) to an LDS tile; then thread (l, part) sums its degree over 32 nodes
+// of the tile against the node weights.  The eight parts and the chunks are
+// added in fixed order; a_lm = A_l - l F_l + d_l G_{l-1}.
+__global__ __launch_bounds__(256) void node_sum_kernel(const double *__restrict__ xn, const double *__restrict__ thn,
+                                                      int n_nodes, int lmax, const double2 *__restrict__ wn,
+                                                      double *__restrict__ state, double *__restrict__ alm) {
+    __shared__ double tile[kNodeLB * kTilePitch];
+    __shared__ double2 wt[kNodeChunk * 3];
+    __shared__ double part[8][kNodeLB][6];
+    __shared__ double fin[kNodeLB][6];
+    __shared__ double coef_a[kNodeLB], coef_b[kNodeLB];
+    __shared__ double gprev[2];
+    const int m = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int n_chunks = (n_nodes + kNodeChunk - 1) / kNodeChunk;
+    double *st = state + (int64_t)m * n_chunks * kNodeChunk * 4;   // (v_prev, v_cur, f, E) per node
+    // seed: y_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) s^m, as mantissa x 2^E
+    double cm2 = (2.0 * m + 1.0) * kInv4Pi;
+    for (int k = 1; k <= m; ++k) cm2 *= (2.0 * k - 1.0) / (2.0 * k);
+    const double cm = sqrt(cm2) * ((m & 1) ? -1.0 : 1.0);
+    for (int c = 0; c < n_chunks; ++c) {
+        const int n = c * kNodeChunk + tid;
+        double vp = 0.0, vc = 0.0, f = 0.0;
+        int E = 0;
+        if (n < n_nodes) {
+            int es;
+            double b = frexp(sin(thn[n]), &es), r = 1.0;
+            int e = 0, eb = es;
+            for (int k = m; k > 0; k >>= 1) {
+                if (k & 1) {
+                    int t;
+                    r = frexp(r * b, &t);
+                    e += t + eb;
+                }
+                int t2;
+                b = frexp(b * b, &t2);
+                eb = 2 * eb + t2;
+            }
+            vc = cm * r;
+            E = e;
+            f = pow2i(E);
+        }
+        double *s = st + ((int64_t)c * kNodeChunk + tid) * 4;
+        s[0] = vp;
+        s[1] = vc;
+        s[2] = f;
+        s[3] = (double)E;
+    }
+    if (tid == 0) gprev[0] = gprev[1] = 0.0;
+    const int lanel = tid % kNodeLB, partid = tid / kNodeLB;   // 32 degrees x 8 parts
+    for (int l0 = m; l0 <= lmax; l0 += kNodeLB) {
+        const int nl = lmax + 1 - l0 < kNodeLB ? lmax + 1 - l0 : kNodeLB;
+        if (tid < kNodeLB) {   // recurrence coefficients of the block
+            const int l = l0 + tid;
+            double a = 0.0, b = 0.0;
+            if (l > m && l <= lmax) {
+                const double ll = (double)l, mm = (double)m;
+                a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+                b = l > m + 1 ? sqrt((2.0 * ll + 1.0) * ((ll - 1.0) * (ll - 1.0) - mm * mm) /
+                                     ((2.0 * ll - 3.0) * (ll * ll - mm * mm)))
+                              : 0.0;
+            }
+            coef_a[tid] = a;
+            coef_b[tid] = b;
+        }
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < n_chunks; ++c) {
+            __syncthreads();   // coefficients ready; tile and weights free
+            const int n = c * kNodeChunk + tid;
+            double *s = st + ((int64_t)c * kNodeChunk + tid) * 4;
+            double vp = s[0], vc = s[1], f = s[2];
+            int E = (int)s[3];
+            const double x = n < n_nodes ? xn[n] : 0.0;
+            for (int k = 0; k < nl; ++k) {
+                const int l = l0 + k;
+                if (l > m) {
+                    const double nv = fma(coef_a[k] * x, vc, -coef_b[k] * vp);
+                    vp = vc;
+                    vc = nv;
+                }
+                tile[k * kTilePitch + tid] = n < n_nodes ? vc * f : 0.0;
+                if ((k & 7) == 7 && fabs(vc) > 0x1p600) {
+                    vc *= 0x1p-600;
+                    vp *= 0x1p-600;
+                    E += 600;
+                    f = pow2i(E);
+                }
+            }
+            s[0] = vp;
+            s[1] = vc;
+            s[2] = f;
+            s[3] = (double)E;
+            for (int k = 0; k < 3; ++k)
+                wt[tid * 3 + k] = n < n_nodes ? wn[((int64_t)m * n_nodes + n) * 3 + k] : make_double2(0.0, 0.0);
+            __syncthreads();
+            if (lanel < nl) {
+#pragma unroll 4
+                for (int q = 0; q < kNodeChunk / 8; ++q) {
+                    const int nn = partid * (kNodeChunk / 8) + q;
+                    const double y = tile[lanel * kTilePitch + nn];
+                    const double2 a = wt[nn * 3], b = wt[nn * 3 + 1], g = wt[nn * 3 + 2];
+                    acc[0] = fma(a.x, y, acc[0]);
+                    acc[1] = fma(a.y, y, acc[1]);
+                    acc[2] = fma(b.x, y, acc[2]);
+                    acc[3] = fma(b.y, y, acc[3]);
+                    acc[4] = fma(g.x, y, acc[4]);
+                    acc[5] = fma(g.y, y, acc[5]);
+                }
+            }
+        }
+        for (int k = 0; k < 6; ++k) part[partid][lanel][k] = acc[k];
+        __syncthreads();
+        if (tid < nl) {   // degree l0 + tid: the eight parts in order
+            double s6[6] = {0, 0, 0, 0, 0, 0};
+            for (int p = 0; p < 8; ++p)
+                for (int i = 0; i < 6; ++i) s6[i] += part[p][tid][i];
+            for (int i = 0; i < 6; ++i) fin[tid][i] = s6[i];
+        }
+        __syncthreads();
+        if (tid == 0) {   // a_lm = A_l - l F_l + d_l G_{l-1}, G carried across blocks
+            for (int k = 0; k < nl; ++k) {
+                const int l = l0 + k;
+                double re = fin[k][0] - l * fin[k][2], im = fin[k][1] - l * fin[k][3];
+                if (l > m) {
+                    const double ll = (double)l, mm = (double)m;
+                    const double d = sqrt((2.0 * ll + 1.0) / (2.0 * ll - 1.0) * (ll * ll - mm * mm));
+                    re = fma(d, gprev[0], re);
+                    im = fma(d, gprev[1], im);
+                }
+                gprev[0] = fin[k][4];
+                gprev[1] = fin[k][5];
+                const int64_t idx = hp_index(lmax, l, m);
+                alm[2 * idx] = re;
+                alm[2 * idx + 1] = im;
+            }
+        }
+    }
+}
+
+unsigned grid_for(int64_t count, int threads, int64_t cap) {
+    int64_t b = (count + threads - 1) / threads;
+    if (b < 1) b = 1;
+    return (unsigned)(b > cap ? cap : b);
+}
+
+}  // namespace
+
+SplinePlan spline_plan(int64_t n, int lmax, int n_nodes) {
+    SplinePlan p;
+    p.n_int = n_nodes - 1;
+    p.n_pass = (lmax + kBinM) / kBinM;
+    p.n_chunks = (n_nodes + kNodeChunk - 1) / kNodeChunk;
+    p.v_doubles = (size_t)(lmax + 1) * p.n_int * 8;
+    p.wn_doubles = (size_t)(lmax + 1) * n_nodes * 6;
+    p.state_doubles = (size_t)(lmax + 1) * p.n_chunks * kNodeChunk * 4;
+    (void)n;
+    return p;
+}
+
+hipError_t launch_spline_count(const double *theta, int64_t n, double theta_cut, double h, int n_nodes, double *xn,
+                               double *thn, unsigned *counts, hipStream_t stream) {
+    const int nb = n_nodes;   // n_int intervals + the polar bucket
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, counts, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nodes_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, stream, theta_cut, h, n_nodes, xn, thn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n > 0) {
+        hipLaunchKernelGGL(count_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, n, theta_cut, h,
+                           n_nodes - 1, counts);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_spline_scatter(const double *theta, const double *phi, const double *w, int64_t n, double theta_cut,
+                                 double h, int n_nodes, const double *xn, const unsigned *counts, int64_t *offsets,
+                                 unsigned *cursors, double *q, int64_t n_spline, double *pth, double *pph, double *pw,
+                                 hipStream_t stream) {
+    const int nb = n_nodes;
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, counts, nb, offsets, cursors);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, phi, w, n, theta_cut,
+                       h, n_nodes - 1, xn, (const int64_t *)offsets, cursors, q, n_spline, pth, pph, pw);
+    return hipGetLastError();
+}
+
+hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
+                                   const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
+                                   double2 *wn, double *state, double *alm, hipStream_t stream) {
+    const int64_t units = (int64_t)p.n_int * p.n_pass;
+    const int64_t per_xcd = (units + 7) / 8;
+    hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(per_xcd * 8)), dim3(kBinThreads), 0, stream, q, n_spline, offsets,
+                       p.n_int, lmax, p.n_pass, per_xcd, v);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t total = (int64_t)(lmax + 1) * n_nodes;
+    hipLaunchKernelGGL(node_weights_kernel, dim3(grid_for(total, 256, 65536)), dim3(256), 0, stream,
+                       (const double2 *)v, xn, n_nodes, lmax, wn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(node_sum_kernel, dim3(lmax + 1), dim3(256), 0, stream, xn, thn, n_nodes, lmax,
+                       (const double2 *)wn, state, alm);
+    return hipGetLastError();
+}
+
+}  // namespace ptalm

@@ -63,6 +63,8 @@ _coupling = _sig("ptalm_coupling_matrix", ctypes.c_int, [_vp, ctypes.c_int, _vp,
 _bp_count = _sig("ptalm_bandpower_count", ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int])
 _bandpowers = _sig("ptalm_bandpowers", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                      ctypes.c_int, ctypes.c_int, _vp, _vp, _vp])
+_alm_spline = _sig("ptalm_alm_from_points_spline", ctypes.c_int,
+                   [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _vp])
 _prepare_call = _sig("ptalm_prepare_call", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
 _autotune = _sig("ptalm_autotune", ctypes.c_int,
                  [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts), _vp])
@@ -260,6 +262,26 @@ def bandpowers(cl_hat, M, lmax: int, delta_l: int, lmin: int = 0, mode: int = 0,
     _check(_bandpowers(_ptr(cl_hat), _ptr(M), None if Wl is None else _ptr(Wl), -1 if Wl is None else Wl.numel() - 1,
                        lmax, lmin, delta_l, mode, _ptr(cb), _ptr(window), _stream(stream)))
     return cb, window
+
+
+def alm_from_points_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float, out=None, stream=None):
+    """a_lm by the interpolated transform of App. A.2 (cubic Hermite splines on n_nodes nodes
+    uniform in theta over [theta_cut, pi - theta_cut]; the polar caps by the exact sum).
+    Same layout as alm_from_points with one weight vector."""
+    _dev_f64(theta, "theta"); _dev_f64(phi, "phi"); _dev_f64(w, "w")
+    n = theta.numel()
+    if phi.numel() != n or w.numel() != n:
+        raise ValueError("theta, phi and w must have the same length")
+    T = alm_size(lmax)
+    if out is None:
+        out = torch.empty(2 * T, dtype=torch.float64, device=theta.device)
+    else:
+        _dev_f64(out, "out")
+        if out.numel() != 2 * T:
+            raise ValueError("out has the wrong size")
+    _check(_alm_spline(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, n_nodes, float(theta_cut), _ptr(out),
+                       _stream(stream)))
+    return out
 
 
 def prepare_call(n: int, lmax: int, options: Opts | None = None):
