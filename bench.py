@@ -15,6 +15,11 @@ Workloads (--workload):
   multi2048    1e7 masked positions shared by 32 lognormal weight vectors, lmax 2048,
                split-bf16 MFMA form; tuned by the library's autotuner on a prefix,
                then each step replays one captured HIP graph (transform + 32 spectra)
+  spline3072   the randoms3072 catalog through the interpolated transform of App. A.2:
+               cubic Hermite splines on pi (lmax+1) + 1 nodes uniform in theta (the
+               spacing of 2 (lmax+1) nodes uniform in x at the equator), polar caps
+               theta < 1 deg by the exact sum; value = point.(l,m) terms of the exact sum
+               it replaces per second; error vs the exact GPU sum on the first 2e6 points
   coupling3072 mode coupling and bandpowers from a window spectrum W_l (l <= 6144) and a
                pseudo-spectrum (l <= 3072): shot noise of 1e8 unit-weight randoms scaled by
                alpha, M_ll' (l, l' <= 3072) with the shot noise removed from W, decoupled
@@ -56,6 +61,8 @@ WORKLOADS = {
     "fullsky64": dict(desc="full-sky uniform n=1e4, unit weights, lmax=64", lmax=64),
     "served": dict(desc="Poisson stream 50/s of masked catalogs, n log-uniform [1e4, 1e7], lmax uniform in "
                         "{128,256,512,1024,2048}, lognormal sigma=0.3 weights, through the request server", lmax=2048),
+    "spline3072": dict(desc="masked randoms n=1e8, unit weights, lmax=3072, interpolated transform (App. A.2): "
+                            "pi (lmax+1) + 1 = 9655 spline nodes uniform in theta, polar caps < 1 deg by the exact sum", lmax=3072),
     "coupling3072": dict(desc="mode coupling lmax=3072 from W_l to 6144 (shot noise of n=1e8 unit-weight randoms "
                               "removed), decoupled and normalised bandpowers delta_l=25 from l=2", lmax=3072),
     "multi2048": dict(desc="one masked position set n=1e7 shared by 32 lognormal weight vectors (sigma=0.2), "
@@ -98,7 +105,7 @@ def tri(lmax):
 
 def make_catalogs(name, scale):
     from paper_2312_12285_amd import synth
-    if name == "randoms3072":
+    if name in ("randoms3072", "spline3072"):
         return [("randoms", synth.masked_randoms(int(1e8 * scale), seed=31))]
     if name == "galaxies1024":
         return [("galaxies", synth.masked_galaxies(int(2e6 * scale), seed_pos=21, seed_w=22)),
@@ -259,6 +266,93 @@ def run_multi(args, cats, lmax):
         print("[bench] cpu baseline (oracle, weight vector 0)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline([("positions with weight vector 0",
                                               synth.Catalog(cat.theta, cat.phi, cat.w[0]))], lmax, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+SPLINE_CUT_DEG = 1.0
+SPLINE_FLOPS_PER_TERM = 22      # per (point, m) of the binning: 4 complex x real multiply-adds + the phase rotation
+
+
+def spline_nodes(lmax):
+    return int(round(math.pi * (lmax + 1))) + 1
+
+
+def run_spline(args, cats, lmax):
+    """spline3072: the interpolated transform on the randoms3072 catalog."""
+    import numpy as np
+    import torch
+    from oracle import ref, spline
+    from paper_2312_12285_amd import ptalm
+    cat = cats[0][1]
+    n = cat.n
+    nodes = spline_nodes(lmax)
+    cut = math.radians(SPLINE_CUT_DEG)
+    t = torch.as_tensor(cat.theta).cuda(); p = torch.as_tensor(cat.phi).cuda(); w = torch.as_tensor(cat.w).cuda()
+    T = tri(lmax)
+    out = torch.empty(2 * T, dtype=torch.float64, device="cuda")
+    ptalm.prepare(lmax)     # the polar part's direct-sum tables, outside the timed region
+    for i in range(args.warmup):
+        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
+        ptalm.alm_from_points_spline(t, p, w, lmax, nodes, cut, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        ptalm.alm_from_points_spline(t, p, w, lmax, nodes, cut, out=out)
+        ev[i][1].record()
+        cl = ptalm.cl_from_alm(out, lmax)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    call_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    theta = cat.theta
+    n_polar = int(((theta < cut) | (theta > math.pi - cut)).sum())
+    flops = SPLINE_FLOPS_PER_TERM * (n - n_polar) * (lmax + 1)
+    achieved = flops / (call_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "whole ptalm_alm_from_points_spline call (binning kernel dominant)",
+                "kernel_ms_per_launch": round(call_ms, 3), "flops_per_point_m": SPLINE_FLOPS_PER_TERM,
+                "timed_span": "one call, HIP events on its stream (incl. its single synchronisation)"}
+    line = {"metric": METRIC, "value": n * T * args.steps / elapsed, "unit": UNIT + " (of the exact sum replaced)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": WORKLOADS["spline3072"]["desc"], "lmax": lmax, "points": n, "nodes": nodes,
+                       "theta_cut_deg": SPLINE_CUT_DEG, "polar_points": n_polar},
+            "roofline": roofline}
+    if not args.no_check:
+        print("[bench] error vs the exact GPU sum on the first 2e6 points", file=sys.stderr, flush=True)
+        k = min(n, 2_000_000)
+        a_s = ptalm.alm_from_points_spline(t[:k].contiguous(), p[:k].contiguous(), w[:k].contiguous(), lmax, nodes, cut)
+        a_d = ptalm.alm_from_points(t[:k].contiguous(), p[:k].contiguous(), w[:k].contiguous(), lmax)
+        line["interpolation_error_first_2e6"] = per_l_errors(ptalm.as_complex(a_s).cpu().numpy(),
+                                                             ptalm.as_complex(a_d).cpu().numpy(), lmax)
+        print("[bench] sampled parity with the oracle's interpolated transform (full catalog)", file=sys.stderr,
+              flush=True)
+        pairs = [(0, 0), (2, 1), (100, 0), (1536, 700), (3072, 0), (3072, 3000)]
+        t1 = time.time()
+        want = spline.alm_spline_entries(cat.theta, cat.phi, cat.w, lmax, nodes, cut, pairs)
+        a = ptalm.as_complex(out).cpu().numpy()
+        got = np.array([a[ptalm.alm_index(lmax, l, m)] for l, m in pairs])
+        clh = ptalm.cl_from_alm(out, lmax).cpu().numpy()
+        scale = np.sqrt(np.maximum(clh[[l for l, _ in pairs]], 1e-300))
+        line["parity"] = {"entries": [f"({l},{m})" for l, m in pairs],
+                          "max_err_over_rms_l": float((np.abs(got - want) / scale).max()),
+                          "oracle_seconds": round(time.time() - t1, 1)}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle interpolated transform, sampled coefficients)", file=sys.stderr,
+              flush=True)
+        pairs = [(3072, 0), (3072, 1536), (2048, 100), (1000, 999), (500, 7), (3072, 3072), (10, 5), (1536, 1)]
+        k = 1_000_000
+        t1 = time.time()
+        spline.alm_spline_entries(cat.theta[:k], cat.phi[:k], cat.w[:k], lmax, nodes, cut, pairs)
+        dt = time.time() - t1
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        line["cpu_baseline"] = {"value": k * len(pairs) / dt, "unit": UNIT + " (of the exact sum replaced)",
+                                "cores": nthreads, "kind": "oracle",
+                                "sample": f"{len(pairs)} coefficients (l, m) of the first {k} points, lmax {lmax}, "
+                                          f"{nodes} nodes ({dt:.1f} s; node values by the C oracle, binning in numpy)"}
     print(json.dumps(line), flush=True)
 
 
@@ -529,6 +623,8 @@ def main():
         del src, dst
     if args.workload == "multi2048":
         return run_multi(args, cats, lmax)
+    if args.workload == "spline3072":
+        return run_spline(args, cats, lmax)
     dev = []
     for name, c in cats:
         dev.append((name, torch.as_tensor(c.theta).cuda(), torch.as_tensor(c.phi).cuda(),

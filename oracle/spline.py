@@ -93,7 +93,9 @@ def binned_weights(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float):
     for m in range(lmax + 1):
         e = ww * np.exp(-1j * m * ph)
         for a in range(4):
-            np.add.at(v[m, :, a], jj, e * c[a])
+            z = e * c[a]
+            v[m, :, a] = (np.bincount(jj, weights=z.real, minlength=n_nodes - 1)
+                          + 1j * np.bincount(jj, weights=z.imag, minlength=n_nodes - 1))
     return v
 
 
@@ -120,3 +122,48 @@ def alm_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float, tables=
         th = np.asarray(theta)[polar]; ph = np.asarray(phi)[polar]; ww = np.asarray(w)[polar]
         out += ref.alm_from_points(th, ph, ww, lmax)
     return out
+
+
+def alm_spline_entries(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float, pairs):
+    """Single coefficients a_lm of the interpolated transform, for sampled checks on
+    catalogs too large for the full tables: the node values come from the oracle's
+    single-entry sums, the binned weights are formed for each sampled m only."""
+    theta = np.asarray(theta, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    x_nodes, th_nodes, _ = nodes(n_nodes, theta_cut)
+    j = interval_of(theta, n_nodes, theta_cut)
+    keep = j >= 0
+    jj = j[keep]
+    x = np.cos(theta[keep])
+    c = hermite_basis((x - x_nodes[jj]) / (x_nodes[jj + 1] - x_nodes[jj]))
+    ph, ww = phi[keep], w[keep]
+    dx = np.diff(x_nodes)
+    polar = ~keep
+    out = []
+    vcache = {}
+    for l, m in pairs:
+        if m not in vcache:
+            e = ww * np.exp(-1j * m * ph)
+            v = np.zeros((n_nodes - 1, 4), dtype=np.complex128)
+            for a in range(4):
+                z = e * c[a]
+                v[:, a] = (np.bincount(jj, weights=z.real, minlength=n_nodes - 1)
+                           + 1j * np.bincount(jj, weights=z.imag, minlength=n_nodes - 1))
+            vcache[m] = v
+        v = vcache[m]
+        ls = np.array([l, max(l - 1, m)])
+        ms = np.array([m, m])
+        yv = np.empty(n_nodes)
+        yp = np.empty(n_nodes)
+        for n, t in enumerate(th_nodes):
+            vals = ref.alm_entries(np.array([t]), np.zeros(1), np.ones(1), ls, ms).real
+            yv[n] = vals[0]
+            yp[n] = vals[1] if l > m else 0.0
+        cl = math.sqrt((2 * l + 1) / (2 * l - 1) * (l - m) * (l + m)) if l > m else 0.0
+        dy = (-l * x_nodes * yv + cl * yp) / (1.0 - x_nodes * x_nodes)
+        a = (v[:, 0] @ yv[:-1] + (v[:, 1] * dx) @ dy[:-1] + v[:, 2] @ yv[1:] + (v[:, 3] * dx) @ dy[1:])
+        if polar.any():
+            a += ref.alm_entries(theta[polar], phi[polar], w[polar], np.array([l]), np.array([m]))[0]
+        out.append(a)
+    return np.array(out)

@@ -123,3 +123,15 @@ def test_planted_spline_mistake_is_caught(oracle, tmp_path, name):
         except Exception:
             results.append(False)
     assert not all(results), f"planted mistake {name!r} passed every spline pin"
+
+
+def test_entries_match_the_full_oracle(oracle):
+    """The single-coefficient form used for full-size sampled checks equals the full form."""
+    from oracle import spline
+    t, p, w = _catalog(5000, 21)
+    lmax, nn, cut = 20, 40, math.radians(7)
+    full = spline.alm_spline(t, p, w, lmax, nn, cut)
+    pairs = [(0, 0), (5, 0), (20, 3), (20, 20), (7, 6)]
+    got = spline.alm_spline_entries(t, p, w, lmax, nn, cut, pairs)
+    idx = [m * (2 * lmax + 1 - m) // 2 + l for l, m in pairs]
+    assert np.abs(got - full[idx]).max() <= 1e-14 * np.abs(full[idx]).max()
