@@ -591,6 +591,8 @@ def main():
     ap.add_argument("--served-requests", type=int, default=500)
     ap.add_argument("--served-slots", type=int, default=4)
     ap.add_argument("--served-arena-gb", type=float, default=4.0)
+    ap.add_argument("--spline-error-table", action="store_true",
+                    help="print the oracle's pointwise spline interpolation errors (CPU only) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (counter runs scale FETCH/WRITE_SIZE by it)")
     args = ap.parse_args()
@@ -599,6 +601,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
               "in DESIGN.md, not built", file=sys.stderr)
         sys.exit(2)
+    if args.spline_error_table:
+        print(json.dumps(spline_error_table()))
+        return
     if args.workload == "served":        # generates its catalogs in worker processes before touching the GPU
         return run_served(args)
 

@@ -167,3 +167,31 @@ def alm_spline_entries(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float,
             a += ref.alm_entries(theta[polar], phi[polar], w[polar], np.array([l]), np.array([m]))[0]
         out.append(a)
     return np.array(out)
+
+
+def ylm_values(l: int, m: int, theta):
+    """y_lm and y_{l-1,m} at each theta (one oracle entry sum per point)."""
+    ls = np.array([l, max(l - 1, m)])
+    ms = np.array([m, m])
+    out = np.empty((2, len(theta)))
+    for k, t in enumerate(np.asarray(theta, dtype=np.float64)):
+        v = ref.alm_entries(np.array([t]), np.zeros(1), np.ones(1), ls, ms).real
+        out[0, k] = v[0]
+        out[1, k] = v[1] if l > m else 0.0
+    return out
+
+
+def interpolation_error(l: int, m: int, x_nodes, x_eval):
+    """Max |S(x) - y_lm(x)| over x_eval for the Hermite spline of App. A.2 on x_nodes
+    (ascending), and max |y_lm| there."""
+    x_nodes = np.asarray(x_nodes, dtype=np.float64)
+    x_eval = np.asarray(x_eval, dtype=np.float64)
+    yn = ylm_values(l, m, np.arccos(x_nodes))
+    c = math.sqrt((2 * l + 1) / (2 * l - 1) * (l - m) * (l + m)) if l > m else 0.0
+    dyn = (-l * x_nodes * yn[0] + c * yn[1]) / (1.0 - x_nodes * x_nodes)
+    j = np.clip(np.searchsorted(x_nodes, x_eval, side="right") - 1, 0, len(x_nodes) - 2)
+    dx = x_nodes[j + 1] - x_nodes[j]
+    b = hermite_basis((x_eval - x_nodes[j]) / dx)
+    s = b[0] * yn[0][j] + b[1] * dx * dyn[j] + b[2] * yn[0][j + 1] + b[3] * dx * dyn[j + 1]
+    y = ylm_values(l, m, np.arccos(x_eval))[0]
+    return float(np.abs(s - y).max()), float(np.abs(y).max())

@@ -545,7 +545,7 @@ int ptalm_alm_from_points_spline(const double *theta, const double *phi, const d
         return fail_hip(e, "reading the polar count");
     const int64_t n_polar = n_polar_u, n_spline = n - n_polar;
     double *q, *pth, *pph, *pw;
-    if ((e = mem.get((void **)&q, sizeof(double) * 5 * (size_t)n_spline)) != hipSuccess ||
+    if ((e = mem.get((void **)&q, sizeof(double) * 8 * (size_t)n_spline)) != hipSuccess ||
         (e = mem.get((void **)&pth, sizeof(double) * (size_t)n_polar)) != hipSuccess ||
         (e = mem.get((void **)&pph, sizeof(double) * (size_t)n_polar)) != hipSuccess ||
         (e = mem.get((void **)&pw, sizeof(double) * (size_t)n_polar)) != hipSuccess)

@@ -31,6 +31,8 @@ namespace {
 
 constexpr double kPi = 3.141592653589793;
 constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+constexpr int kPointDoubles = 8;   // doubles per sorted point record
 
 __device__ inline int interval_of(double th, double theta_cut, double h, int n_int) {
     if (th < theta_cut || th > kPi - theta_cut) return n_int;   // polar bucket
@@ -90,8 +92,9 @@ __global__ __launch_bounds__(1024) void scan_kernel(const unsigned *__restrict__
     if (tid == 1023) offsets[nb] = run;
 }
 
-// Points of the spline region in interval order with q_a = w c_a(t) and the
-// phase; polar points (bucket n_int) to their own arrays.  The order inside an
+// Points of the spline region in interval order, one 64-byte record each:
+// (w c_0(t), w c_1(t), w c_2(t), w c_3(t), phi / (2 pi), cos phi, sin phi, 0);
+// polar points (bucket n_int) to their own arrays.  The order inside an
 // interval is the order of the atomic increments.
 __global__ void scatter_kernel(const double *__restrict__ theta, const double *__restrict__ phi,
                                const double *__restrict__ w, int64_t n, double theta_cut, double h, int n_int,
@@ -112,44 +115,71 @@ __global__ void scatter_kernel(const double *__restrict__ theta, const double *_
         const double x = cos(th);
         const double t = (x - xn[j]) / (xn[j + 1] - xn[j]);
         const double u = 1.0 - t;
-        q[pos] = wi * ((2.0 * t + 1.0) * u * u);
-        q[n_spline + pos] = wi * (t * u * u);
-        q[2 * n_spline + pos] = wi * (t * t * (3.0 - 2.0 * t));
-        q[3 * n_spline + pos] = wi * (t * t * (t - 1.0));
-        q[4 * n_spline + pos] = ph;
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        double2 *dst = (double2 *)(q + pos * kPointDoubles);
+        dst[0] = make_double2(wi * ((2.0 * t + 1.0) * u * u), wi * (t * u * u));
+        dst[1] = make_double2(wi * (t * t * (3.0 - 2.0 * t)), wi * (t * t * (t - 1.0)));
+        dst[2] = make_double2(ph * kInv2Pi, cp);
+        dst[3] = make_double2(sp, 0.0);
     }
 }
 
-constexpr int kBinM = 16;        // orders per binning workgroup
-constexpr int kBinThreads = 256;
+constexpr int kBinM = 8;         // orders per binning wave
+constexpr int kBinThreads = 64;  // one wave per (interval, kBinM orders)
+constexpr int kBinVals = kBinM * 8;   // sums per wave: 4 basis functions x (re, im) per order
 
-// v[((m n_int) + j) * 4 + a] (complex) for the orders [16 p, 16 p + 16) of interval j.
-// Workgroups are numbered so that consecutive ones (the passes over the same
-// interval) land on the same XCD and reuse its L2 copy of the interval's points.
-__global__ __launch_bounds__(kBinThreads) void bin_kernel(const double *__restrict__ q, int64_t n_spline,
+// v[((m n_int) + j) * 4 + a] (complex) for the orders [kBinM p, kBinM (p + 1)) of interval j,
+// one wavefront each.  Wavefronts are numbered so that consecutive ones (the
+// passes over the same interval) land on the same XCD and reuse its L2 copy of
+// the interval's points.  Each lane sums a strided subset of the points (loading
+// its next point while it sums the current one); the 64 sums per lane are then
+// added across the wave.
+__global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__restrict__ q, int64_t n_spline,
                                                           const int64_t *__restrict__ offsets, int n_int, int lmax,
                                                           int n_pass, int64_t units_per_xcd,
                                                           double2 *__restrict__ v) {
-    __shared__ double red[kBinThreads][33];
-    __shared__ double red2[8][32];
     const int64_t L = (int64_t)(blockIdx.x & 7) * units_per_xcd + (blockIdx.x >> 3);
     const int j = (int)(L / n_pass), pass = (int)(L % n_pass);
     if (j >= n_int) return;
     const int m0 = pass * kBinM;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     double acc[kBinM][8];
 #pragma unroll
     for (int mm = 0; mm < kBinM; ++mm)
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[mm][c] = 0.0;
     const int64_t lo = offsets[j], hi = offsets[j + 1];
-    for (int64_t r = lo + tid; r < hi; r += kBinThreads) {
-        const double q0 = q[r], q1 = q[n_spline + r], q2 = q[2 * n_spline + r], q3 = q[3 * n_spline + r];
-        const double ph = q[4 * n_spline + r];
-        double s1, c1, sm, cm;
-        sincos(ph, &s1, &c1);
-        sincos((double)m0 * ph, &sm, &cm);
-        double zr = cm, zi = -sm;          // e^{-i m phi}
+    if (hi <= lo) {   // empty interval: its sums are zero
+        for (int flat = lane; flat < kBinVals; flat += 64) {
+            const int mm = flat >> 3, c = flat & 7;
+            if (m0 + mm <= lmax) ((double *)(v + ((int64_t)(m0 + mm) * n_int + j) * 4 + c / 2))[c & 1] = 0.0;
+        }
+        return;
+    }
+    // e^{-i m0 phi} from the reduced argument m0 phi / (2 pi) mod 1, taken exactly
+    // (two-product of m0 and phi / (2 pi)), so sincospi sees a small argument.
+    // The next point's record is loaded (unconditionally, at a clamped index)
+    // while the current one is summed.
+    const double2 *rec = (const double2 *)q;
+    double2 nx[4];
+    auto fetch = [&](int64_t r) {
+        const int64_t rr = r < hi ? r : hi - 1;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) nx[a] = rec[rr * 4 + a];
+    };
+    fetch(lo + lane);
+    for (int64_t r = lo + lane; r < hi; r += kBinThreads) {
+        const double2 c01 = nx[0], c23 = nx[1], pc = nx[2], s0 = nx[3];
+        fetch(r + kBinThreads);
+        const double q0 = c01.x, q1 = c01.y, q2 = c23.x, q3 = c23.y;
+        const double tph = pc.x, c1 = pc.y, s1 = s0.x;
+        const double p = (double)m0 * tph;
+        const double pe = fma((double)m0, tph, -p);
+        const double fr = (p - floor(p)) + pe;      // m0 phi / (2 pi) mod 1, within 2^-52
+        double sm, cm;
+        sincospi(2.0 * fr, &sm, &cm);
+        double zr = cm, zi = -sm;          // e^{-i m0 phi}
         const double ur = c1, ui = -s1;    // e^{-i phi}
 #pragma unroll
         for (int mm = 0; mm < kBinM; ++mm) {
@@ -166,31 +196,32 @@ __global__ __launch_bounds__(kBinThreads) void bin_kernel(const double *__restri
             zr = nr;
         }
     }
-    // sum over the workgroup in fixed order, 32 values per round through LDS
+    // reduce-scatter butterflies over the wave, 64 values at a time: at each step
+    // a lane keeps one half of its values and adds its partner's copy of that
+    // half; lane k ends with the total of value 64 g + k (= 8 mm + c), always
+    // in the same order of additions
 #pragma unroll
-    for (int round = 0; round < kBinM * 8 / 32; ++round) {
+    for (int g = 0; g < kBinVals / 64; ++g) {
+        double vals[64];
 #pragma unroll
-        for (int c = 0; c < 32; ++c) red[tid][c] = acc[(round * 32 + c) / 8][(round * 32 + c) % 8];
-        __syncthreads();
-        {
-            const int vi = tid & 31, g = tid >> 5;
-            double s = 0.0;
-            for (int k = 0; k < 32; ++k) s += red[32 * g + k][vi];
-            red2[g][vi] = s;
-        }
-        __syncthreads();
-        if (tid < 32) {
-            double s = 0.0;
-            for (int g = 0; g < 8; ++g) s += red2[g][tid];
-            const int flat = round * 32 + tid;
-            const int mm = flat / 8, c = flat % 8;
-            const int m = m0 + mm;
-            if (m <= lmax) {
-                double *dst = (double *)(v + ((int64_t)m * n_int + j) * 4 + c / 2);
-                dst[c & 1] = s;
+        for (int k = 0; k < 64; ++k) vals[k] = acc[(64 * g + k) >> 3][k & 7];
+#pragma unroll
+        for (int half = 32; half >= 1; half >>= 1) {
+            const bool upper = (lane & half) != 0;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const double send = upper ? vals[i] : vals[half + i];
+                const double keep = upper ? vals[half + i] : vals[i];
+                vals[i] = keep + __shfl_xor(send, half);
             }
         }
-        __syncthreads();
+        const int flat = 64 * g + lane;
+        const int mm = flat >> 3, c = flat & 7;
+        const int m = m0 + mm;
+        if (m <= lmax) {
+            double *dst = (double *)(v + ((int64_t)m * n_int + j) * 4 + c / 2);
+            dst[c & 1] = vals[0];
+        }
     }
 }
 
@@ -230,40 +261,42 @@ __global__ void node_weights_kernel(const double2 *__restrict__ v, const double 
 }
 
 constexpr int kNodeChunk = 256;   // nodes per tile (one per thread in the recurrence phase)
-constexpr int kNodeLB = 32;       // degrees per tile
+constexpr int kNodeLB = 16;       // degrees per tile
 constexpr int kTilePitch = kNodeChunk + 1;
+constexpr int kNodeParts = 256 / kNodeLB;   // node groups summed separately in phase 2
 
 // exact 2^e for the range used here, 0 below the double range
 __device__ inline double pow2i(int e) { return e < -1074 ? 0.0 : ldexp(1.0, e); }
 
-// One workgroup per order m.  Per block of 32 degrees and per chunk of 256
-// nodes: each thread advances its node's recurrence (state kept in global
-// scratch between blocks, as a scaled pair with a binary exponent) and writes
-// y_l(x_n) to an LDS tile; then thread (l, part) sums its degree over 32 nodes
-// of the tile against the node weights.  The eight parts and the chunks are
-// added in fixed order; a_lm = A_l - l F_l + d_l G_{l-1}.
+// One workgroup per order m.  Chunks of 256 nodes in order; per chunk each
+// thread carries its node's recurrence in registers (a scaled pair with a
+// binary exponent) through all degrees, 16 at a time: it writes y_l(x_n) of
+// the block to an LDS tile, then thread (l, part) sums its degree over 16
+// nodes of the tile against the node weights, the 16 parts are added in order
+// and the block's sums are accumulated over the chunks (in chunk order) in
+// sums[idx(l, m)][6] = (A, F, G) as complex pairs.  Finally
+// a_lm = A_l - l F_l + d_l G_{l-1}.
 __global__ __launch_bounds__(256) void node_sum_kernel(const double *__restrict__ xn, const double *__restrict__ thn,
                                                       int n_nodes, int lmax, const double2 *__restrict__ wn,
-                                                      double *__restrict__ state, double *__restrict__ alm) {
+                                                      double *__restrict__ sums, double *__restrict__ alm) {
     __shared__ double tile[kNodeLB * kTilePitch];
     __shared__ double2 wt[kNodeChunk * 3];
-    __shared__ double part[8][kNodeLB][6];
-    __shared__ double fin[kNodeLB][6];
+    __shared__ double part[kNodeParts][kNodeLB][6];
     __shared__ double coef_a[kNodeLB], coef_b[kNodeLB];
-    __shared__ double gprev[2];
     const int m = blockIdx.x;
     const int tid = threadIdx.x;
     const int n_chunks = (n_nodes + kNodeChunk - 1) / kNodeChunk;
-    double *st = state + (int64_t)m * n_chunks * kNodeChunk * 4;   // (v_prev, v_cur, f, E) per node
-    // seed: y_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) s^m, as mantissa x 2^E
+    const int lanel = tid % kNodeLB, partid = tid / kNodeLB;   // 16 degrees x 16 parts
+    // seed factor (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)); y_mm = factor s^m
     double cm2 = (2.0 * m + 1.0) * kInv4Pi;
     for (int k = 1; k <= m; ++k) cm2 *= (2.0 * k - 1.0) / (2.0 * k);
     const double cm = sqrt(cm2) * ((m & 1) ? -1.0 : 1.0);
     for (int c = 0; c < n_chunks; ++c) {
         const int n = c * kNodeChunk + tid;
-        double vp = 0.0, vc = 0.0, f = 0.0;
+        const bool live = n < n_nodes;
+        double vp = 0.0, vc = 0.0, f = 0.0, x = 0.0;
         int E = 0;
-        if (n < n_nodes) {
+        if (live) {   // s^m as mantissa x 2^E by binary powering with renormalisation
             int es;
             double b = frexp(sin(thn[n]), &es), r = 1.0;
             int e = 0, eb = es;
@@ -280,46 +313,39 @@ __global__ __launch_bounds__(256) void node_sum_kernel(const double *__restrict_
             vc = cm * r;
             E = e;
             f = pow2i(E);
+            x = xn[n];
         }
-        double *s = st + ((int64_t)c * kNodeChunk + tid) * 4;
-        s[0] = vp;
-        s[1] = vc;
-        s[2] = f;
-        s[3] = (double)E;
-    }
-    if (tid == 0) gprev[0] = gprev[1] = 0.0;
-    const int lanel = tid % kNodeLB, partid = tid / kNodeLB;   // 32 degrees x 8 parts
-    for (int l0 = m; l0 <= lmax; l0 += kNodeLB) {
-        const int nl = lmax + 1 - l0 < kNodeLB ? lmax + 1 - l0 : kNodeLB;
-        if (tid < kNodeLB) {   // recurrence coefficients of the block
-            const int l = l0 + tid;
-            double a = 0.0, b = 0.0;
-            if (l > m && l <= lmax) {
-                const double ll = (double)l, mm = (double)m;
-                a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
-                b = l > m + 1 ? sqrt((2.0 * ll + 1.0) * ((ll - 1.0) * (ll - 1.0) - mm * mm) /
-                                     ((2.0 * ll - 3.0) * (ll * ll - mm * mm)))
-                              : 0.0;
-            }
-            coef_a[tid] = a;
-            coef_b[tid] = b;
-        }
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        for (int c = 0; c < n_chunks; ++c) {
-            __syncthreads();   // coefficients ready; tile and weights free
-            const int n = c * kNodeChunk + tid;
-            double *s = st + ((int64_t)c * kNodeChunk + tid) * 4;
-            double vp = s[0], vc = s[1], f = s[2];
-            int E = (int)s[3];
-            const double x = n < n_nodes ? xn[n] : 0.0;
-            for (int k = 0; k < nl; ++k) {
-                const int l = l0 + k;
+        __syncthreads();   // the previous chunk's last reads of wt are done
+        for (int k = 0; k < 3; ++k)
+            wt[tid * 3 + k] = live ? wn[((int64_t)m * n_nodes + n) * 3 + k] : make_double2(0.0, 0.0);
+        for (int l0 = m; l0 <= lmax; l0 += kNodeLB) {
+            const int nl = lmax + 1 - l0 < kNodeLB ? lmax + 1 - l0 : kNodeLB;
+            double g6[6] = {0, 0, 0, 0, 0, 0};
+            if (tid < nl) {
+                const int l = l0 + tid;
+                if (c > 0) {   // running sums of the earlier chunks (loaded early)
+                    const double *src = sums + hp_index(lmax, l, m) * 6;
+                    for (int i = 0; i < 6; ++i) g6[i] = src[i];
+                }
+                double a = 0.0, bb = 0.0;
                 if (l > m) {
+                    const double ll = (double)l, mm = (double)m;
+                    a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+                    bb = l > m + 1 ? sqrt((2.0 * ll + 1.0) * ((ll - 1.0) * (ll - 1.0) - mm * mm) /
+                                          ((2.0 * ll - 3.0) * (ll * ll - mm * mm)))
+                                   : 0.0;
+                }
+                coef_a[tid] = a;
+                coef_b[tid] = bb;
+            }
+            __syncthreads();   // coefficients ready; tile free
+            for (int k = 0; k < nl; ++k) {
+                if (l0 + k > m) {
                     const double nv = fma(coef_a[k] * x, vc, -coef_b[k] * vp);
                     vp = vc;
                     vc = nv;
                 }
-                tile[k * kTilePitch + tid] = n < n_nodes ? vc * f : 0.0;
+                tile[k * kTilePitch + tid] = live ? vc * f : 0.0;
                 if ((k & 7) == 7 && fabs(vc) > 0x1p600) {
                     vc *= 0x1p-600;
                     vp *= 0x1p-600;
@@ -327,17 +353,12 @@ __global__ __launch_bounds__(256) void node_sum_kernel(const double *__restrict_
                     f = pow2i(E);
                 }
             }
-            s[0] = vp;
-            s[1] = vc;
-            s[2] = f;
-            s[3] = (double)E;
-            for (int k = 0; k < 3; ++k)
-                wt[tid * 3 + k] = n < n_nodes ? wn[((int64_t)m * n_nodes + n) * 3 + k] : make_double2(0.0, 0.0);
             __syncthreads();
+            double acc[6] = {0, 0, 0, 0, 0, 0};
             if (lanel < nl) {
 #pragma unroll 4
-                for (int q = 0; q < kNodeChunk / 8; ++q) {
-                    const int nn = partid * (kNodeChunk / 8) + q;
+                for (int q = 0; q < kNodeChunk / kNodeParts; ++q) {
+                    const int nn = partid * (kNodeChunk / kNodeParts) + q;
                     const double y = tile[lanel * kTilePitch + nn];
                     const double2 a = wt[nn * 3], b = wt[nn * 3 + 1], g = wt[nn * 3 + 2];
                     acc[0] = fma(a.x, y, acc[0]);
@@ -348,33 +369,31 @@ __global__ __launch_bounds__(256) void node_sum_kernel(const double *__restrict_
                     acc[5] = fma(g.y, y, acc[5]);
                 }
             }
-        }
-        for (int k = 0; k < 6; ++k) part[partid][lanel][k] = acc[k];
-        __syncthreads();
-        if (tid < nl) {   // degree l0 + tid: the eight parts in order
-            double s6[6] = {0, 0, 0, 0, 0, 0};
-            for (int p = 0; p < 8; ++p)
-                for (int i = 0; i < 6; ++i) s6[i] += part[p][tid][i];
-            for (int i = 0; i < 6; ++i) fin[tid][i] = s6[i];
-        }
-        __syncthreads();
-        if (tid == 0) {   // a_lm = A_l - l F_l + d_l G_{l-1}, G carried across blocks
-            for (int k = 0; k < nl; ++k) {
-                const int l = l0 + k;
-                double re = fin[k][0] - l * fin[k][2], im = fin[k][1] - l * fin[k][3];
-                if (l > m) {
-                    const double ll = (double)l, mm = (double)m;
-                    const double d = sqrt((2.0 * ll + 1.0) / (2.0 * ll - 1.0) * (ll * ll - mm * mm));
-                    re = fma(d, gprev[0], re);
-                    im = fma(d, gprev[1], im);
-                }
-                gprev[0] = fin[k][4];
-                gprev[1] = fin[k][5];
-                const int64_t idx = hp_index(lmax, l, m);
-                alm[2 * idx] = re;
-                alm[2 * idx + 1] = im;
+            for (int k = 0; k < 6; ++k) part[partid][lanel][k] = acc[k];
+            __syncthreads();
+            if (tid < nl) {   // degree l0 + tid: the parts in order, then the chunk total
+                double s6[6] = {0, 0, 0, 0, 0, 0};
+                for (int p = 0; p < kNodeParts; ++p)
+                    for (int i = 0; i < 6; ++i) s6[i] += part[p][tid][i];
+                double *dst = sums + hp_index(lmax, l0 + tid, m) * 6;
+                for (int i = 0; i < 6; ++i) dst[i] = g6[i] + s6[i];
             }
         }
+    }
+    __syncthreads();   // every chunk's sums are visible to the workgroup
+    for (int l = m + tid; l <= lmax; l += blockDim.x) {
+        const double *s6 = sums + hp_index(lmax, l, m) * 6;
+        double re = s6[0] - l * s6[2], im = s6[1] - l * s6[3];
+        if (l > m) {
+            const double ll = (double)l, mm = (double)m;
+            const double d = sqrt((2.0 * ll + 1.0) / (2.0 * ll - 1.0) * (ll * ll - mm * mm));
+            const double *gp = sums + hp_index(lmax, l - 1, m) * 6;
+            re = fma(d, gp[4], re);
+            im = fma(d, gp[5], im);
+        }
+        const int64_t idx = hp_index(lmax, l, m);
+        alm[2 * idx] = re;
+        alm[2 * idx + 1] = im;
     }
 }
 
@@ -393,7 +412,7 @@ SplinePlan spline_plan(int64_t n, int lmax, int n_nodes) {
     p.n_chunks = (n_nodes + kNodeChunk - 1) / kNodeChunk;
     p.v_doubles = (size_t)(lmax + 1) * p.n_int * 8;
     p.wn_doubles = (size_t)(lmax + 1) * n_nodes * 6;
-    p.state_doubles = (size_t)(lmax + 1) * p.n_chunks * kNodeChunk * 4;
+    p.state_doubles = (size_t)tri_size(lmax) * 6;   // node sums (A, F, G) per (l, m)
     (void)n;
     return p;
 }
@@ -430,6 +449,7 @@ hipError_t launch_spline_scatter(const double *theta, const double *phi, const d
 hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
                                    double2 *wn, double *state, double *alm, hipStream_t stream) {
+    double *sums = state;
     const int64_t units = (int64_t)p.n_int * p.n_pass;
     const int64_t per_xcd = (units + 7) / 8;
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(per_xcd * 8)), dim3(kBinThreads), 0, stream, q, n_spline, offsets,
@@ -441,7 +461,7 @@ hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t
                        (const double2 *)v, xn, n_nodes, lmax, wn);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(node_sum_kernel, dim3(lmax + 1), dim3(256), 0, stream, xn, thn, n_nodes, lmax,
-                       (const double2 *)wn, state, alm);
+                       (const double2 *)wn, sums, alm);
     return hipGetLastError();
 }
 
