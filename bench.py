@@ -20,6 +20,10 @@ Workloads (--workload):
                spacing of 2 (lmax+1) nodes uniform in x at the equator), polar caps
                theta < 1 deg by the exact sum; value = point.(l,m) terms of the exact sum
                it replaces per second; error vs the exact GPU sum on the first 2e6 points
+  shear3072    1e7 clustered masked galaxies (lognormal weights) with shear components
+               g1, g2 ~ N(0, 0.26^2), lmax 3072: the spin +-2 transform to E and B
+               (ptalm_shear_alm_from_points) and the EE, BB, EB spectra; value =
+               point.(l,m) terms per second, one term covering both spins
   coupling3072 mode coupling and bandpowers from a window spectrum W_l (l <= 6144) and a
                pseudo-spectrum (l <= 3072): shot noise of 1e8 unit-weight randoms scaled by
                alpha, M_ll' (l, l' <= 3072) with the shot noise removed from W, decoupled
@@ -51,6 +55,7 @@ FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128
 BF16_PEAK_TFLOPS = 2500.0     # MI355X dense bf16 matrix peak
 MULTI_FLOPS_PER_TERM = 4      # per (point, l, m, weight vector): re and im multiply-adds
 FLOPS_PER_TERM = 7            # recurrence multiply + FMA, two accumulate FMAs
+SPIN_FLOPS_PER_TERM = 16      # spin +-2: two step factors, two chains, four accumulate FMAs
 METRIC = "point\u00b7(l,m) terms/s FP64 vs mixed at stated rel err; served p50/p99 latency"
 UNIT = "point\u00b7(l,m) terms/s"
 
@@ -63,6 +68,8 @@ WORKLOADS = {
                         "{128,256,512,1024,2048}, lognormal sigma=0.3 weights, through the request server", lmax=2048),
     "spline3072": dict(desc="masked randoms n=1e8, unit weights, lmax=3072, interpolated transform (App. A.2): "
                             "pi (lmax+1) + 1 = 9655 spline nodes uniform in theta, polar caps < 1 deg by the exact sum", lmax=3072),
+    "shear3072": dict(desc="masked galaxies n=1e7 (2% jittered copies, lognormal sigma=0.3) with shear g1, g2 ~ "
+                           "N(0, 0.26^2), lmax=3072, spin +-2 transform to E and B modes + EE/BB/EB spectra", lmax=3072),
     "coupling3072": dict(desc="mode coupling lmax=3072 from W_l to 6144 (shot noise of n=1e8 unit-weight randoms "
                               "removed), decoupled and normalised bandpowers delta_l=25 from l=2", lmax=3072),
     "multi2048": dict(desc="one masked position set n=1e7 shared by 32 lognormal weight vectors (sigma=0.2), "
@@ -110,6 +117,8 @@ def make_catalogs(name, scale):
     if name == "galaxies1024":
         return [("galaxies", synth.masked_galaxies(int(2e6 * scale), seed_pos=21, seed_w=22)),
                 ("randoms", synth.masked_randoms(int(2e7 * scale), seed=23))]
+    if name == "shear3072":
+        return [("galaxies", synth.masked_galaxies(int(1e7 * scale), seed_pos=61, seed_w=62))]
     if name == "fullsky64":
         return [("points", synth.fullsky_uniform(10_000, seed=1))]
     if name == "multi2048":
@@ -354,6 +363,114 @@ def run_spline(args, cats, lmax):
                                 "sample": f"{len(pairs)} coefficients (l, m) of the first {k} points, lmax {lmax}, "
                                           f"{nodes} nodes ({dt:.1f} s; node values by the C oracle, binning in numpy)"}
     print(json.dumps(line), flush=True)
+
+
+SHEAR_PAIRS = [(2, 0), (2, 2), (3, 1), (100, 37), (1536, 700), (3072, 3072), (3072, 3000), (3071, 1)]
+
+
+def run_shear(args, cats, lmax):
+    """shear3072: spin +-2 transform to E/B of a shear catalog and its three spectra."""
+    import numpy as np
+    import torch
+    from oracle import ref
+    from paper_2312_12285_amd import ptalm, synth
+    cat = cats[0][1]
+    n = cat.n
+    g1, g2 = synth.shear_components(n, seed=63)
+    d = [torch.as_tensor(a).cuda() for a in (cat.theta, cat.phi, cat.w, g1, g2)]
+    T = tri(lmax)
+    e = torch.empty(2 * T, dtype=torch.float64, device="cuda")
+    b = torch.empty(2 * T, dtype=torch.float64, device="cuda")
+    cls = [torch.empty(lmax + 1, dtype=torch.float64, device="cuda") for _ in range(3)]
+    opt = ptalm.opts(points_per_lane=args.points_per_lane, l_block=args.l_block, timing=1)
+    kernel_ms = []
+
+    def step():
+        ptalm.shear_alm_from_points(*d, lmax, out_e=e, out_b=b, options=opt)
+        kernel_ms.append(ptalm.last_timing_ms())
+        ptalm.cl_from_alm(e, lmax, out=cls[0])
+        ptalm.cl_from_alm(b, lmax, out=cls[1])
+        ptalm.cross_cl(e, b, lmax, out=cls[2])
+
+    for i in range(args.warmup):
+        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
+        step()
+    torch.cuda.synchronize()
+    kernel_ms.clear()
+    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    terms = n * T
+    k_ms = float(np.mean(kernel_ms))
+    achieved = SPIN_FLOPS_PER_TERM * terms / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "spin_direct_kernel<4, 8>" if not (args.points_per_lane or args.l_block) else
+                          f"spin_direct_kernel<{args.points_per_lane or 4}, {args.l_block or 8}>",
+                "kernel_ms_per_launch": round(k_ms, 3), "flops_per_term": SPIN_FLOPS_PER_TERM}
+    line = {"metric": METRIC, "value": terms * args.steps / elapsed, "unit": UNIT + " (spin +-2, both spins per term)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": WORKLOADS["shear3072"]["desc"], "lmax": lmax, "points": n, "terms_per_step": terms},
+            "roofline": roofline}
+    if not args.no_check:
+        print("[bench] sampled parity against the oracle's spin entries (every point)", file=sys.stderr, flush=True)
+        t1 = time.time()
+        ls = [l for l, _ in SHEAR_PAIRS]
+        ms = [m for _, m in SHEAR_PAIRS]
+        we, wb = ref.shear_eb_entries(cat.theta, cat.phi, cat.w, g1, g2, ls, ms)
+        ge, gb = ptalm.as_complex(e).cpu().numpy(), ptalm.as_complex(b).cpu().numpy()
+        idx = [ptalm.alm_index(lmax, l, m) for l, m in SHEAR_PAIRS]
+        cle, clb = cls[0].cpu().numpy(), cls[1].cpu().numpy()
+        err = max(float((np.abs(ge[idx] - we) / np.sqrt(cle[ls])).max()),
+                  float((np.abs(gb[idx] - wb) / np.sqrt(clb[ls])).max()))
+        line["parity"] = {"entries": [f"({l},{m})" for l, m in SHEAR_PAIRS], "max_err_over_rms_l": err,
+                          "oracle_seconds": round(time.time() - t1, 1)}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle spin transform on a prefix)", file=sys.stderr, flush=True)
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        k = 64
+        t1 = time.time()
+        ref.shear_eb(cat.theta[:k], cat.phi[:k], cat.w[:k], g1[:k], g2[:k], lmax, nthreads=nthreads)
+        dt = time.time() - t1
+        k2 = int(min(n, max(k, k * args.cpu_seconds / max(dt, 1e-3))))
+        if k2 > k:
+            t1 = time.time()
+            ref.shear_eb(cat.theta[:k2], cat.phi[:k2], cat.w[:k2], g1[:k2], g2[:k2], lmax, nthreads=nthreads)
+            dt = time.time() - t1
+            k = k2
+        line["cpu_baseline"] = {"value": k * T / dt, "unit": UNIT + " (spin +-2, both spins per term)",
+                                "cores": nthreads, "kind": "oracle",
+                                "sample": f"first {k} galaxies at lmax {lmax} ({k * T:.3g} terms, {dt:.1f} s)"}
+    print(json.dumps(line), flush=True)
+
+
+def spline_error_table():
+    """Pointwise interpolation error of y_lm(x) for the configurations of the paper's figure on
+    it (l = 500; m = 0, 125, 250; N_x = N_l/2, N_l, 2 N_l with N_l = 501), with the nodes
+    uniform in x over [-1, 1] and with the same number uniform in theta, evaluated on
+    |x| <= 3/4 (the paper's equatorial region).  CPU only (the oracle)."""
+    import numpy as np
+    from oracle import spline
+    l, Nl = 500, 501
+    x_eval = np.linspace(-0.75, 0.75, 6001)
+    rows = []
+    for nx in (Nl // 2, Nl, 2 * Nl):
+        xu = np.linspace(-1.0, 1.0, nx)
+        xu = xu[np.abs(xu) < 0.9]
+        th = np.linspace(math.pi, 0.0, nx)
+        xt = np.cos(th)
+        xt = xt[np.abs(xt) < 0.9]
+        for m in (0, 125, 250):
+            eu, amp = spline.interpolation_error(l, m, xu, x_eval)
+            et, _ = spline.interpolation_error(l, m, xt, x_eval)
+            rows.append({"N_x": nx, "l": l, "m": m, "max_abs_err_x_uniform": eu, "max_abs_err_theta_uniform": et,
+                         "max_abs_y": amp})
+    return rows
 
 
 COUPLING_LW = 6144
@@ -630,6 +747,8 @@ def main():
         return run_multi(args, cats, lmax)
     if args.workload == "spline3072":
         return run_spline(args, cats, lmax)
+    if args.workload == "shear3072":
+        return run_shear(args, cats, lmax)
     dev = []
     for name, c in cats:
         dev.append((name, torch.as_tensor(c.theta).cuda(), torch.as_tensor(c.phi).cuda(),

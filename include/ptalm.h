@@ -219,9 +219,39 @@ int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, in
 int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
                                  int n_nodes, double theta_cut, double *alm, void *stream);
 
+/*
+ * Spin-weighted transform for shear (spin +-2 harmonics in place of Y_lm, the
+ * generalisation the paper notes at the end of Sec. 4).  For a catalog with
+ * weights w and shear components (g1, g2) it forms
+ *     _{+2}a_lm = sum_i w_i (g1_i + i g2_i) _{+2}Y*_lm(theta_i, phi_i),
+ *     _{-2}a_lm = sum_i w_i (g1_i - i g2_i) _{-2}Y*_lm(theta_i, phi_i),
+ * and writes the E and B modes
+ *     alm_E = -(_{+2}a + _{-2}a) / 2,   alm_B = i (_{+2}a - _{-2}a) / 2
+ * with _sY_lm(theta, phi) = (-1)^m sqrt((2l+1)/4pi) d^l_{m,-s}(theta) e^{i m phi}
+ * (Wigner d; the convention of Goldberg et al. 1967 and healpy's E/B signs).
+ * theta, phi, w, g1, g2: device, n doubles each (structure of arrays).
+ * alm_E, alm_B: device, 2*T doubles each, healpy order (complex interleaved),
+ * written completely (0 for l < 2).  FP64 throughout.
+ * opts: NULL for defaults; honours points_per_lane, l_block (a compiled
+ * spin variant), n_slices, m_ranges and timing (ptalm_last_timing then reads
+ * the spin kernel's device time); precision must be PTALM_FP64 and n_weights
+ * 0 or 1 (else PTALM_ENOTSUP).  Allocates and frees stream-ordered scratch of
+ * ptalm_shear_workspace_bytes(n, lmax, opts) bytes; builds the spin tables for
+ * lmax on first use (synchronously).  Deterministic: the same inputs give the
+ * same bits.  PTALM_EINVAL on bad sizes or pointers.
+ */
+int ptalm_shear_alm_from_points(const double *theta, const double *phi, const double *w, const double *g1,
+                                const double *g2, int64_t n, int lmax, double *alm_E, double *alm_B,
+                                const ptalm_opts *opts, void *stream);
+
+/* Scratch bytes of ptalm_shear_alm_from_points for these arguments (0 on bad
+ * arguments).  Host only. */
+size_t ptalm_shear_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts);
+
 /* Device time of the transform kernel(s) of the last ptalm_alm_from_points_ex
- * call made on this thread with opts->timing set: from just before the first
- * transform kernel to just after the last one, on that call's stream.  Blocks
+ * or ptalm_shear_alm_from_points call made on this thread with opts->timing
+ * set: from just before the first transform kernel to just after the last
+ * one, on that call's stream.  Blocks
  * until that work has finished.  PTALM_EINVAL if no timed call was made.
  * Host only. */
 int ptalm_last_timing(double *transform_ms);

@@ -411,3 +411,205 @@ int ptalm_ref_coupling_rows(const double *Wl, int lmax_w, int lmax, const int *r
         for (int lp = 0; lp <= lmax; ++lp) out[(int64_t)k * (lmax + 1) + lp] = coupling_entry(Wl, lmax_w, rows[k], lp);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Spin-weighted transform for shear (spin +-2 harmonics, end of Sec. 4).
+ * _sY_lm(theta, phi) = (-1)^m sqrt((2l+1)/4pi) d^l_{m,-s}(theta) e^{i m phi}
+ * (Goldberg et al. 1967).  For fixed (m, mp) the Wigner d obey
+ *   l sqrt(((l+1)^2-m^2)((l+1)^2-mp^2)) d^{l+1}
+ *     = (2l+1) (l(l+1) cos theta - m mp) d^l - (l+1) sqrt((l^2-m^2)(l^2-mp^2)) d^{l-1},
+ * started at l0 = max(m, |mp|), where the Wigner sum has one term:
+ *   l0 = m:   d^m_{m,mp} = sqrt(C(2m, m+mp)) cos^{m+mp}(theta/2) sin^{m-mp}(theta/2);
+ *   l0 = 2 > m (mp = +-2, m = 0, 1): from the same sum,
+ *     d^2_{0,+-2} = sqrt(6) c^2 s^2,  d^2_{1,-2} = 2 c s^3,  d^2_{1,2} = -2 c^3 s.
+ * ------------------------------------------------------------------------- */
+
+/* sqrt(C(2m, m+2)) as mantissa * 2^exponent (running product, renormalised). */
+static void spin_seed_constant(int m, long double *f_out, long *e_out)
+{
+    long double f = 1.0L;
+    long e = 0;
+    for (int k = 1; k <= m + 2; ++k) {      /* C(2m, m+2) = prod_k (m-2+k)/k */
+        int t;
+        f = frexpl(f * ((long double)(m - 2 + k) / (long double)k), &t);
+        e += t;
+    }
+    if (e & 1) { f *= 2.0L; e -= 1; }
+    *f_out = sqrtl(f);
+    *e_out = e / 2;
+}
+
+/* d^l_{m,mp}(theta) for mp = +-2 and l0 <= l <= lend (0 while below 2^-900):
+ * written to d[l] when d != NULL; the value at lend is returned. */
+static double spin_column(double c, double s, double x, int m, int mp, int lend, long double kf, long ke,
+                          const double *A, const double *B, const double *C, double *d)
+{
+    const int l0 = m > 2 ? m : 2;
+    double f;
+    long e = 0;
+    if (m >= 2) {
+        double fc, fs;
+        long ec, es;
+        pow_with_exponent(c, m + mp, &fc, &ec);
+        pow_with_exponent(s, m - mp, &fs, &es);
+        int t;
+        f = frexp((double)kf * fc * fs, &t);
+        e = ke + ec + es + t;
+    } else if (m == 0) {
+        f = sqrt(6.0) * c * c * s * s;
+    } else {
+        f = (mp < 0) ? 2.0 * c * s * s * s : -2.0 * c * c * c * s;
+    }
+    if (e > -900) { f = ldexp(f, (int)e); e = 0; }
+    double prev = 0.0, cur = f;              /* d^{l-1}, d^l scaled by 2^-e */
+    if (d) d[l0] = (e == 0) ? cur : 0.0;
+    for (int l = l0; l < lend; ++l) {
+        double v = (A[l] * x - B[l]) * cur - C[l] * prev;
+        if (e < 0) {
+            if (fabs(v) > 0x1p600) {
+                v *= 0x1p-600;
+                cur *= 0x1p-600;
+                e += 600;
+            }
+            int ve;
+            frexp(v, &ve);
+            if (v != 0.0 && (long)ve + e > -900) {
+                v = ldexp(v, (int)e);
+                cur = ldexp(cur, (int)e);
+                e = 0;
+            }
+        }
+        prev = cur;
+        cur = v;
+        if (d) d[l + 1] = (e == 0) ? cur : 0.0;
+    }
+    return (e == 0) ? cur : 0.0;
+}
+
+/* A, B, C of the step l -> l+1 for l0 <= l < lend (index l). */
+static void spin_coefficients(int m, int mp, int lend, double *A, double *B, double *C)
+{
+    for (int l = (m > 2 ? m : 2); l < lend; ++l) {
+        const double dl = l, l1 = l + 1.0, dm = m, dp = mp;
+        const double D = dl * sqrt((l1 * l1 - dm * dm) * (l1 * l1 - dp * dp));
+        A[l] = (2.0 * l + 1.0) * dl * l1 / D;
+        B[l] = (2.0 * l + 1.0) * dm * dp / D;
+        C[l] = l1 * sqrt((dl * dl - dm * dm) * (dl * dl - dp * dp)) / D;
+    }
+}
+
+int ptalm_ref_spin_entries(const double *theta, const double *phi, const double *w, const double *g1,
+                           const double *g2, int64_t n, int count, const int *ls, const int *ms, double *out,
+                           int nthreads)
+{
+    if (n < 0 || count < 0 || out == NULL || (count > 0 && (ls == NULL || ms == NULL))) return -1;
+    if (n > 0 && (theta == NULL || phi == NULL || w == NULL || g1 == NULL || g2 == NULL)) return -1;
+    int lmax_all = 2;
+    for (int k = 0; k < count; ++k) {
+        if (ms[k] < 0 || ls[k] < ms[k] || ls[k] < 2) return -1;
+        if (ls[k] > lmax_all) lmax_all = ls[k];
+    }
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+    const int64_t nchunk = (n + ENTRY_CHUNK - 1) / ENTRY_CHUNK;
+    long double *part = malloc(sizeof(long double) * 4 * (size_t)(nchunk > 0 ? nchunk : 1));
+    double *co = malloc(sizeof(double) * 6 * (size_t)(lmax_all + 1));
+    if (!part || !co) { free(part); free(co); return -1; }
+    for (int k = 0; k < count; ++k) {
+        const int l = ls[k], m = ms[k];
+        double *Ap = co, *Bp = co + (lmax_all + 1), *Cp = co + 2 * (lmax_all + 1);   /* mp = -2: s = +2 */
+        double *Am = co + 3 * (lmax_all + 1), *Bm = co + 4 * (lmax_all + 1), *Cm = co + 5 * (lmax_all + 1);
+        spin_coefficients(m, -2, l, Ap, Bp, Cp);
+        spin_coefficients(m, 2, l, Am, Bm, Cm);
+        long double kf = 1.0L;
+        long ke = 0;
+        if (m >= 2) spin_seed_constant(m, &kf, &ke);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+        for (int64_t ch = 0; ch < nchunk; ++ch) {
+            long double pr = 0.0L, pi = 0.0L, mr = 0.0L, mi = 0.0L;
+            int64_t i1 = (ch + 1) * ENTRY_CHUNK;
+            if (i1 > n) i1 = n;
+            for (int64_t i = ch * ENTRY_CHUNK; i < i1; ++i) {
+                const double c = cos(0.5 * theta[i]), s = sin(0.5 * theta[i]);
+                const double x = (c - s) * (c + s);
+                const double dp = spin_column(c, s, x, m, -2, l, kf, ke, Ap, Bp, Cp, NULL);
+                const double dm = spin_column(c, s, x, m, 2, l, kf, ke, Am, Bm, Cm, NULL);
+                if (dp == 0.0 && dm == 0.0) continue;
+                const long double ang = (long double)m * (long double)phi[i];
+                const long double er = cosl(ang), ei = -sinl(ang);      /* e^{-i m phi} */
+                const long double a = g1[i], b = g2[i], ww = w[i];
+                /* w (a + i b) d+ e^{-i m phi} and w (a - i b) d- e^{-i m phi} */
+                pr += ww * dp * (a * er - b * ei);
+                pi += ww * dp * (a * ei + b * er);
+                mr += ww * dm * (a * er + b * ei);
+                mi += ww * dm * (a * ei - b * er);
+            }
+            part[4 * ch] = pr;
+            part[4 * ch + 1] = pi;
+            part[4 * ch + 2] = mr;
+            part[4 * ch + 3] = mi;
+        }
+        long double acc[4] = {0.0L, 0.0L, 0.0L, 0.0L};
+        for (int64_t ch = 0; ch < nchunk; ++ch)
+            for (int q = 0; q < 4; ++q) acc[q] += part[4 * ch + q];
+        long double norm = sqrtl((2.0L * l + 1.0L) / (4.0L * PI_L));
+        if (m & 1) norm = -norm;
+        for (int q = 0; q < 4; ++q) out[4 * k + q] = (double)(norm * acc[q]);
+    }
+    free(part);
+    free(co);
+    return 0;
+}
+
+int ptalm_ref_spin_alm(const double *theta, const double *phi, const double *w, const double *g1,
+                       const double *g2, int64_t n, int lmax, double *alm_p2, double *alm_m2, int nthreads)
+{
+    if (check_args(theta, phi, w, n, lmax, alm_p2) || alm_m2 == NULL || (n > 0 && (g1 == NULL || g2 == NULL)))
+        return -1;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+    memset(alm_p2, 0, sizeof(double) * 2 * (size_t)tri_size(lmax));
+    memset(alm_m2, 0, sizeof(double) * 2 * (size_t)tri_size(lmax));
+    if (lmax < 2) return 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int m = 0; m <= lmax; ++m) {
+        const int l0 = m > 2 ? m : 2;
+        double *co = malloc(sizeof(double) * 6 * (size_t)(lmax + 1));
+        double *dp = malloc(sizeof(double) * (size_t)(lmax + 1));
+        double *dm = malloc(sizeof(double) * (size_t)(lmax + 1));
+        long double *acc = calloc((size_t)4 * (lmax + 1), sizeof(long double));
+        double *Ap = co, *Bp = co + (lmax + 1), *Cp = co + 2 * (lmax + 1);
+        double *Am = co + 3 * (lmax + 1), *Bm = co + 4 * (lmax + 1), *Cm = co + 5 * (lmax + 1);
+        spin_coefficients(m, -2, lmax, Ap, Bp, Cp);
+        spin_coefficients(m, 2, lmax, Am, Bm, Cm);
+        long double kf = 1.0L;
+        long ke = 0;
+        if (m >= 2) spin_seed_constant(m, &kf, &ke);
+        for (int64_t i = 0; i < n; ++i) {
+            const double c = cos(0.5 * theta[i]), s = sin(0.5 * theta[i]);
+            const double x = (c - s) * (c + s);
+            spin_column(c, s, x, m, -2, lmax, kf, ke, Ap, Bp, Cp, dp);
+            spin_column(c, s, x, m, 2, lmax, kf, ke, Am, Bm, Cm, dm);
+            const long double ang = (long double)m * (long double)phi[i];
+            const long double er = cosl(ang), ei = -sinl(ang);
+            const long double a = g1[i], b = g2[i], ww = w[i];
+            const long double qpr = ww * (a * er - b * ei), qpi = ww * (a * ei + b * er);
+            const long double qmr = ww * (a * er + b * ei), qmi = ww * (a * ei - b * er);
+            for (int l = l0; l <= lmax; ++l) {
+                acc[4 * l] += qpr * dp[l];
+                acc[4 * l + 1] += qpi * dp[l];
+                acc[4 * l + 2] += qmr * dm[l];
+                acc[4 * l + 3] += qmi * dm[l];
+            }
+        }
+        for (int l = l0; l <= lmax; ++l) {
+            long double norm = sqrtl((2.0L * l + 1.0L) / (4.0L * PI_L));
+            if (m & 1) norm = -norm;
+            const int64_t k = hp_index(lmax, l, m);
+            alm_p2[2 * k] = (double)(norm * acc[4 * l]);
+            alm_p2[2 * k + 1] = (double)(norm * acc[4 * l + 1]);
+            alm_m2[2 * k] = (double)(norm * acc[4 * l + 2]);
+            alm_m2[2 * k + 1] = (double)(norm * acc[4 * l + 3]);
+        }
+        free(co); free(dp); free(dm); free(acc);
+    }
+    return 0;
+}

@@ -71,6 +71,26 @@ int ptalm_ref_coupling_matrix(const double *Wl, int lmax_w, int lmax, double *M,
 int ptalm_ref_coupling_rows(const double *Wl, int lmax_w, int lmax, const int *rows, int nrows, double *out,
                             int nthreads);
 
+/* Spin-weighted transform for shear (spin +-2 harmonics, end of Sec. 4),
+ * selected coefficients over every point:
+ *   out[4k..4k+1] = sum_i w_i (g1_i + i g2_i) _{+2}Y*_{l m}(theta_i, phi_i),
+ *   out[4k+2..4k+3] = sum_i w_i (g1_i - i g2_i) _{-2}Y*_{l m}(theta_i, phi_i),
+ * (l, m) = (ls[k], ms[k]), 0 <= m <= l, l >= 2; with
+ * _sY_lm = (-1)^m sqrt((2l+1)/4pi) d^l_{m,-s}(theta) e^{i m phi} (Wigner d).
+ * d from the one-term value at l0 = max(m, 2) by the three-term recurrence in
+ * l (FP64, seed exponent carried separately as in the scalar transform), sums
+ * in long double.  Returns 0, or -1 on bad arguments. */
+int ptalm_ref_spin_entries(const double *theta, const double *phi, const double *w, const double *g1,
+                           const double *g2, int64_t n, int count, const int *ls, const int *ms, double *out,
+                           int nthreads);
+
+/* The same transform for every coefficient: alm_p2 = _{+2}a_lm, alm_m2 = _{-2}a_lm,
+ * healpy order, complex interleaved (2T doubles each; 0 for l < 2).  Parallel
+ * over m; per point the two d columns by the recurrence above, sums in long
+ * double in point order.  Returns 0, or -1 on bad arguments. */
+int ptalm_ref_spin_alm(const double *theta, const double *phi, const double *w, const double *g1,
+                       const double *g2, int64_t n, int lmax, double *alm_p2, double *alm_m2, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

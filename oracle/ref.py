@@ -30,8 +30,12 @@ def _bind(path):
     lib.ptalm_ref_threej000.restype = ctypes.c_double
     lib.ptalm_ref_coupling_matrix.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
     lib.ptalm_ref_coupling_rows.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _dp, ctypes.c_int]
-    for f in ("ptalm_ref_alm_from_points", "ptalm_ref_alm_from_points_ld", "ptalm_ref_alm_entries",
-              "ptalm_ref_cl_from_alm", "ptalm_ref_cross_cl", "ptalm_ref_coupling_matrix", "ptalm_ref_coupling_rows"):
+    lib.ptalm_ref_spin_entries.argtypes = [_dp, _dp, _dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, _ip, _ip, _dp,
+                                           ctypes.c_int]
+    lib.ptalm_ref_spin_alm.argtypes = [_dp, _dp, _dp, _dp, _dp, ctypes.c_int64, ctypes.c_int, _dp, _dp, ctypes.c_int]
+    for f in ("ptalm_ref_alm_from_points", "ptalm_ref_alm_from_points_ld", "ptalm_ref_alm_entries", "ptalm_ref_spin_alm",
+              "ptalm_ref_cl_from_alm", "ptalm_ref_cross_cl", "ptalm_ref_coupling_matrix", "ptalm_ref_coupling_rows",
+              "ptalm_ref_spin_entries"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -115,6 +119,48 @@ def alm_entries(theta, phi, w, ls, ms, nthreads: int = 0) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle rejected the arguments (rc={rc})")
     return out.view(np.complex128)
+
+
+def spin_entries(theta, phi, w, g1, g2, ls, ms, nthreads: int = 0):
+    """Selected spin +-2 coefficients over all points: (_{+2}a, _{-2}a), each complex128,
+    one per (ls[k], ms[k]), for the field g1 + i g2 (spin +2) and its conjugate (spin -2)."""
+    lib = _load()
+    theta, phi, w, g1, g2 = (_f64(a) for a in (theta, phi, w, g1, g2))
+    ls = np.ascontiguousarray(ls, dtype=np.int32)
+    ms = np.ascontiguousarray(ms, dtype=np.int32)
+    out = np.zeros(4 * ls.size, dtype=np.float64)
+    rc = lib.ptalm_ref_spin_entries(_ptr(theta), _ptr(phi), _ptr(w), _ptr(g1), _ptr(g2), theta.size, ls.size,
+                                    ls.ctypes.data_as(_ip), ms.ctypes.data_as(_ip), _ptr(out), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    o = out.reshape(-1, 4)
+    return o[:, 0] + 1j * o[:, 1], o[:, 2] + 1j * o[:, 3]
+
+
+def spin_alm(theta, phi, w, g1, g2, lmax: int, nthreads: int = 0):
+    """(_{+2}a_lm, _{-2}a_lm) for every coefficient, healpy order, complex128 (0 for l < 2)."""
+    lib = _load()
+    theta, phi, w, g1, g2 = (_f64(a) for a in (theta, phi, w, g1, g2))
+    T = alm_size(lmax)
+    p2 = np.zeros(2 * T)
+    m2 = np.zeros(2 * T)
+    rc = lib.ptalm_ref_spin_alm(_ptr(theta), _ptr(phi), _ptr(w), _ptr(g1), _ptr(g2), theta.size, lmax, _ptr(p2),
+                                _ptr(m2), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return p2.view(np.complex128), m2.view(np.complex128)
+
+
+def shear_eb(theta, phi, w, g1, g2, lmax: int, nthreads: int = 0):
+    """E and B coefficients of the whole transform: a^E = -(_2a + _-2a)/2, a^B = i (_2a - _-2a)/2."""
+    a2, am2 = spin_alm(theta, phi, w, g1, g2, lmax, nthreads)
+    return -(a2 + am2) / 2, 1j * (a2 - am2) / 2
+
+
+def shear_eb_entries(theta, phi, w, g1, g2, ls, ms, nthreads: int = 0):
+    """Selected E and B coefficients: a^E = -(_2a + _-2a)/2, a^B = i (_2a - _-2a)/2."""
+    a2, am2 = spin_entries(theta, phi, w, g1, g2, ls, ms, nthreads)
+    return -(a2 + am2) / 2, 1j * (a2 - am2) / 2
 
 
 def cl_from_alm(alm, lmax: int) -> np.ndarray:

@@ -44,6 +44,8 @@ std::mutex g_mu;
 std::map<std::pair<int, int>, ptalm::Tables> g_tables;          // (device, lmax)
 std::map<std::tuple<int, int, int>, int *> g_ranges;            // (device, lmax, R)
 
+std::map<std::pair<int, int>, ptalm::SpinTables> g_spin_tables;  // (device, lmax)
+
 // Kernel choices found by ptalm_autotune, per (device, precision, n_weights,
 // lmax); used for every option left at 0 in later calls.
 struct Tuned {
@@ -574,6 +576,143 @@ int ptalm_alm_from_points_spline(const double *theta, const double *phi, const d
     return PTALM_OK;
 }
 
+namespace {
+
+int get_spin_tables(int lmax, const ptalm::SpinTables **out) {
+    int dev;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_spin_tables.find({dev, lmax});
+    if (it != g_spin_tables.end()) {
+        *out = &it->second;
+        return PTALM_OK;
+    }
+    ptalm::SpinTables t;
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
+    e = ptalm::build_spin_tables(lmax, &t, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+    if (e != hipSuccess) {
+        hipFree(t.coef);
+        hipFree(t.sigma);
+        return fail_hip(e, "building spin tables");
+    }
+    auto res = g_spin_tables.emplace(std::make_pair(dev, lmax), t);
+    *out = &res.first->second;
+    return PTALM_OK;
+}
+
+constexpr int kSpinKP = 4;
+constexpr int kSpinLB = 8;
+
+struct SpinResolved {
+    int kp, lb, S, R;
+    int64_t groups;
+};
+
+int spin_resolve(int64_t n, int lmax, const ptalm_opts *o, SpinResolved *r) {
+    ptalm_opts d;
+    memset(&d, 0, sizeof d);
+    if (!o) o = &d;
+    if (o->n_weights < 0 || o->points_per_lane < 0 || o->l_block < 0 || o->n_slices < 0 || o->m_ranges < 0)
+        return fail(PTALM_EINVAL, "option out of range");
+    if (o->precision != PTALM_FP64) return fail(PTALM_ENOTSUP, "the shear transform is FP64 only");
+    if (o->n_weights > 1) return fail(PTALM_ENOTSUP, "the shear transform takes one weight vector");
+    if (o->n_slices > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
+    r->kp = o->points_per_lane ? o->points_per_lane : kSpinKP;
+    r->lb = o->l_block ? o->l_block : kSpinLB;
+    if (!ptalm::spin_variant_exists(r->kp, r->lb))
+        return fail(PTALM_ENOTSUP, "no spin kernel variant with these points_per_lane / l_block");
+    r->groups = (n + 64 * r->kp - 1) / (64 * r->kp);
+    const int64_t gmax = std::max<int64_t>(1, r->groups);
+    int64_t S = o->n_slices ? o->n_slices : std::min<int64_t>(kMaxSlices, gmax);
+    if (S > gmax) S = gmax;  // every slice holds at least one group, so every partial is written
+    r->S = (int)S;
+    int R = o->m_ranges ? o->m_ranges : (int)std::max<int64_t>(1, kTargetItems / S);
+    if (R > lmax + 1) R = lmax + 1;
+    if ((int64_t)S * R > kMaxItems) return fail(PTALM_EINVAL, "n_slices x m_ranges work items exceed 2^22");
+    r->R = R;
+    return PTALM_OK;
+}
+
+}  // namespace
+
+size_t ptalm_shear_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts) {
+    if (n < 0 || !lmax_ok(lmax)) return 0;
+    SpinResolved r;
+    if (spin_resolve(n, lmax, opts, &r)) return 0;
+    return sizeof(double) * 4 * (size_t)ptalm::tri_size(lmax) * (size_t)r.S;
+}
+
+int ptalm_shear_alm_from_points(const double *theta, const double *phi, const double *w, const double *g1,
+                                const double *g2, int64_t n, int lmax, double *alm_E, double *alm_B,
+                                const ptalm_opts *opts, void *stream_) {
+    g_error.clear();
+    if (n < 0) return fail(PTALM_EINVAL, "n < 0");
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (alm_E == nullptr || alm_B == nullptr) return fail(PTALM_EINVAL, "alm_E or alm_B is NULL");
+    if (n > 0 && (theta == nullptr || phi == nullptr || w == nullptr || g1 == nullptr || g2 == nullptr))
+        return fail(PTALM_EINVAL, "NULL input");
+    SpinResolved r;
+    int rc = spin_resolve(n, lmax, opts, &r);
+    if (rc) return rc;
+    hipStream_t stream = (hipStream_t)stream_;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cap);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone) return fail(PTALM_EINVAL, "the shear transform is not capturable");
+    const int64_t T = ptalm::tri_size(lmax);
+    if (n == 0) {
+        if ((e = ptalm::launch_zero(alm_E, 2 * T, stream)) != hipSuccess ||
+            (e = ptalm::launch_zero(alm_B, 2 * T, stream)) != hipSuccess)
+            return fail_hip(e, "zero kernel launch");
+        return PTALM_OK;
+    }
+    const ptalm::SpinTables *tab;
+    if ((rc = get_spin_tables(lmax, &tab))) return rc;
+    const int *ranges;
+    if ((rc = get_ranges(lmax, r.R, &ranges))) return rc;
+    const bool timed = opts != nullptr && opts->timing != 0;
+    if (timed) {
+        g_timing.valid = false;
+        if (!g_timing.start && (e = hipEventCreate(&g_timing.start)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+        if (!g_timing.stop && (e = hipEventCreate(&g_timing.stop)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+    }
+    AsyncAllocs mem(stream);
+    double *partial;
+    if ((e = mem.get((void **)&partial, sizeof(double) * 4 * (size_t)T * (size_t)r.S)) != hipSuccess)
+        return fail_hip(e, "hipMallocAsync(partial)");
+    ptalm::SpinArgs a;
+    a.theta = theta;
+    a.phi = phi;
+    a.w = w;
+    a.g1 = g1;
+    a.g2 = g2;
+    a.n = n;
+    a.lmax = lmax;
+    a.n_ranges = r.R;
+    a.n_slices = r.S;
+    a.groups = r.groups;
+    a.range_m = ranges;
+    a.coef = tab->coef;
+    a.partial = partial;
+    bool supported = true;
+    if (timed && (e = hipEventRecord(g_timing.start, stream)) != hipSuccess) return fail_hip(e, "hipEventRecord");
+    if ((e = ptalm::launch_spin(a, r.kp, r.lb, stream, &supported)) != hipSuccess) return fail_hip(e, "spin kernel launch");
+    if (!supported) return fail(PTALM_ENOTSUP, "spin kernel variant not compiled");
+    if (timed) {
+        if ((e = hipEventRecord(g_timing.stop, stream)) != hipSuccess) return fail_hip(e, "hipEventRecord");
+        g_timing.valid = true;
+    }
+    if ((e = ptalm::launch_spin_finish(partial, r.S, tab->sigma, lmax, alm_E, alm_B, stream)) != hipSuccess)
+        return fail_hip(e, "spin finish launch");
+    if ((e = mem.release()) != hipSuccess) return fail_hip(e, "hipFreeAsync");
+    return PTALM_OK;
+}
+
 int ptalm_prepare(int lmax) {
     g_error.clear();
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
@@ -705,6 +844,11 @@ int ptalm_release_cache(void) {
         hipFree(kv.second.sigma);
     }
     g_tables.clear();
+    for (auto &kv : g_spin_tables) {
+        hipFree(kv.second.coef);
+        hipFree(kv.second.sigma);
+    }
+    g_spin_tables.clear();
     for (auto &kv : g_ranges) hipFree(kv.second);
     g_ranges.clear();
     g_tuned.clear();

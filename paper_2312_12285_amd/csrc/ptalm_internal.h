@@ -146,6 +146,29 @@ hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
                                    double2 *wn, double *state, double *alm, hipStream_t stream);
 
+// Spin +-2 transform for shear: device tables per lmax, kernel arguments.
+struct SpinTables {
+    int lmax = -1;
+    double2 *coef = nullptr;  // (alpha, beta) step pairs, coef_table_size(lmax)
+    double *sigma = nullptr;  // output scale per (l, m), healpy order; 0 for l < 2
+};
+struct SpinArgs {
+    const double *theta, *phi, *w, *g1, *g2;
+    int64_t n;
+    int lmax;
+    int n_ranges;
+    int n_slices;
+    int64_t groups;           // ceil(n / (64 KP))
+    const int *range_m;       // device, n_ranges+1
+    const double2 *coef;
+    double *partial;          // device, n_slices * 4T doubles
+};
+hipError_t build_spin_tables(int lmax, SpinTables *t, hipStream_t stream);
+bool spin_variant_exists(int kp, int lb);
+hipError_t launch_spin(const SpinArgs &a, int kp, int lb, hipStream_t stream, bool *supported);
+hipError_t launch_spin_finish(const double *partial, int n_slices, const double *sigma, int lmax, double *alm_e,
+                              double *alm_b, hipStream_t stream);
+
 bool multi_nw_supported(int nw);
 hipError_t launch_alm_multi(const MultiArgs &a, hipStream_t stream);
 hipError_t launch_multi_finish(const MultiArgs &a, const double *sigma, double *alm, hipStream_t stream);

@@ -65,6 +65,9 @@ _bandpowers = _sig("ptalm_bandpowers", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_in
                                                      ctypes.c_int, ctypes.c_int, _vp, _vp, _vp])
 _alm_spline = _sig("ptalm_alm_from_points_spline", ctypes.c_int,
                    [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _vp])
+_shear = _sig("ptalm_shear_alm_from_points", ctypes.c_int,
+              [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.c_int, _vp, _vp, ctypes.POINTER(Opts), _vp])
+_shear_ws = _sig("ptalm_shear_workspace_bytes", ctypes.c_size_t, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
 _prepare_call = _sig("ptalm_prepare_call", ctypes.c_int, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
 _autotune = _sig("ptalm_autotune", ctypes.c_int,
                  [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts), _vp])
@@ -282,6 +285,37 @@ def alm_from_points_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: fl
     _check(_alm_spline(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, n_nodes, float(theta_cut), _ptr(out),
                        _stream(stream)))
     return out
+
+
+def shear_alm_from_points(theta, phi, w, g1, g2, lmax: int, out_e=None, out_b=None, options: Opts | None = None,
+                          stream=None):
+    """E and B modes of a weighted shear catalog through the spin +-2 harmonics:
+    a^E = -(_2a + _-2a)/2, a^B = i(_2a - _-2a)/2 with _{+-2}a_lm = sum_i w_i (g1 +- i g2)_i _{+-2}Y*_lm.
+    Returns (alm_E, alm_B), each float64 [2T] in the layout of alm_from_points."""
+    for name, a in (("theta", theta), ("phi", phi), ("w", w), ("g1", g1), ("g2", g2)):
+        _dev_f64(a, name)
+    n = theta.numel()
+    if any(a.numel() != n for a in (phi, w, g1, g2)):
+        raise ValueError("theta, phi, w, g1 and g2 must have the same length")
+    T = alm_size(lmax)
+    outs = []
+    for o in (out_e, out_b):
+        if o is None:
+            o = torch.empty(2 * T, dtype=torch.float64, device=theta.device)
+        else:
+            _dev_f64(o, "out")
+            if o.numel() != 2 * T:
+                raise ValueError("out has the wrong size")
+        outs.append(o)
+    o = options if options is not None else opts()
+    _check(_shear(_ptr(theta), _ptr(phi), _ptr(w), _ptr(g1), _ptr(g2), n, lmax, _ptr(outs[0]), _ptr(outs[1]),
+                  ctypes.byref(o), _stream(stream)))
+    return outs[0], outs[1]
+
+
+def shear_workspace_bytes(n: int, lmax: int, options: Opts | None = None) -> int:
+    o = options if options is not None else opts()
+    return int(_shear_ws(n, lmax, ctypes.byref(o)))
 
 
 def prepare_call(n: int, lmax: int, options: Opts | None = None):

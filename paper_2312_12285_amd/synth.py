@@ -13,6 +13,8 @@ weights.  Workload recipes (stated in the design doc):
   displaced by an isotropic tangent-plane Gaussian (redrawn until inside the
   mask);
 * Gauss-Legendre x uniform-phi quadrature grid (exact orthonormality check);
+* shear components for the spin-2 transform: g1, g2 ~ N(0, 0.26^2) each
+  (intrinsic-ellipticity scatter per component, no coherent signal);
 * golden-spiral point set of Sec. 3.1 (cos theta_k = (1 - (2k+1)/N)/2,
   phi_k = 2 pi k / golden ratio, k < N), optionally perturbed.
 """
@@ -175,6 +177,12 @@ def masked_galaxies(n: int = 2_000_000, seed_pos: int = 21, seed_w: int = 22, si
     """Galaxies in the survey mask with 2% jittered duplicates, lognormal weights."""
     t, p = clustered_in_mask(n, seed_pos)
     return Catalog(t, p, lognormal_weights(n, sigma, seed_w))
+
+
+def shear_components(n: int, seed: int, sigma_e: float = 0.26):
+    """Shear (g1, g2) per galaxy: independent Gaussian components of rms sigma_e."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, sigma_e, n), rng.normal(0.0, sigma_e, n)
 
 
 def masked_randoms(n: int, seed: int) -> Catalog:

@@ -230,3 +230,97 @@ def test_planted_spin_mistake_is_caught(oracle, tmp_path, name):
         except Exception:
             return
     pytest.fail(f"planted mistake {name!r} passed every spin pin")
+
+
+# ---------------------------------------------------------------------------
+# The C form of the spin oracle (selected coefficients over every point, used for
+# sampled checks at full size), pinned against the Python oracle above and against
+# the spin addition theorem at l = 3072.
+# ---------------------------------------------------------------------------
+def c_pin_matches_python(ref):
+    from oracle import spin
+    rng = np.random.default_rng(5)
+    n, lmax = 2000, 48
+    t = np.arccos(rng.uniform(-1, 1, n))
+    t[:4] = [0.0, math.pi, 1e-5, math.pi - 1e-6]
+    p = rng.uniform(0, 2 * math.pi, n)
+    w = rng.lognormal(0, 0.3, n)
+    g1, g2 = rng.normal(0, 0.26, n), rng.normal(0, 0.26, n)
+    G = g1 + 1j * g2
+    a2 = spin.spin_alm(2, t, p, w, G, lmax)
+    am2 = spin.spin_alm(-2, t, p, w, np.conj(G), lmax)
+    pairs = [(l, m) for m in range(lmax + 1) for l in range(max(m, 2), lmax + 1)]
+    idx = [m * (2 * lmax + 1 - m) // 2 + l for l, m in pairs]
+    e2, em2 = ref.spin_entries(t, p, w, g1, g2, [l for l, _ in pairs], [m for _, m in pairs])
+    return (np.abs(e2 - a2[idx]).max() <= 1e-12 * np.abs(a2).max()
+            and np.abs(em2 - am2[idx]).max() <= 1e-12 * np.abs(am2).max())
+
+
+def c_pin_addition_theorem(ref):
+    """sum_{m>=0} |_2Y_lm|^2 + sum_{m>0} |_-2Y_lm|^2 = (2l+1)/4pi at l = 3072 (one point,
+    unit weight, g = 1).  Near the poles the FP64 value of cos(theta) fixes theta only to
+    ~eps/theta, which moves the sum by up to ~(l theta)^2 eps / theta^2: 2e-9 there, 1e-11
+    elsewhere."""
+    L = 3072
+    for th, tol in ((0.3, 1e-11), (1.7, 1e-11), (2.9, 1e-11), (1e-4, 2e-9), (math.pi - 1e-3, 2e-9)):
+        one = np.ones(1)
+        e2, em2 = ref.spin_entries(np.array([th]), np.array([0.7]), one, one, 0 * one,
+                                   np.full(L + 1, L), np.arange(L + 1))
+        tot = np.sum(np.abs(e2) ** 2) + np.sum(np.abs(em2[1:]) ** 2)
+        if abs(tot / ((2 * L + 1) / (4 * math.pi)) - 1) > tol:
+            return False
+    return True
+
+
+def c_pin_full_matches_python(ref):
+    from oracle import spin
+    rng = np.random.default_rng(9)
+    n, lmax = 1500, 40
+    t = np.arccos(rng.uniform(-1, 1, n))
+    t[:2] = [2e-6, math.pi - 3e-5]
+    p = rng.uniform(0, 2 * math.pi, n)
+    w = rng.lognormal(0, 0.3, n)
+    g1, g2 = rng.normal(0, 0.26, n), rng.normal(0, 0.26, n)
+    E, B = spin.shear_eb(t, p, w, g1, g2, lmax)
+    Ec, Bc = ref.shear_eb(t, p, w, g1, g2, lmax)
+    return np.abs(Ec - E).max() <= 1e-12 * np.abs(E).max() and np.abs(Bc - B).max() <= 1e-12 * np.abs(B).max()
+
+
+C_PINS = [c_pin_matches_python, c_pin_addition_theorem, c_pin_full_matches_python]
+
+
+@pytest.mark.parametrize("pin", C_PINS, ids=lambda f: f.__name__)
+def test_spin_c_oracle_pin(oracle, pin):
+    assert pin(oracle)
+
+
+C_MUTANTS = {
+    "c_recurrence_mmp_sign": ("B[l] = (2.0 * l + 1.0) * dm * dp / D;", "B[l] = -(2.0 * l + 1.0) * dm * dp / D;"),
+    "c_lag_factor": ("C[l] = l1 * sqrt((dl * dl - dm * dm) * (dl * dl - dp * dp)) / D;",
+                     "C[l] = dl * sqrt((dl * dl - dm * dm) * (dl * dl - dp * dp)) / D;"),
+    "c_condon_shortley_dropped": ("        if (m & 1) norm = -norm;\n        for (int q", "        for (int q"),
+    "c_seed_constant_off": ("for (int k = 1; k <= m + 2; ++k) {", "for (int k = 1; k <= m + 1; ++k) {"),
+    "c_shear_sign": ("pr += ww * dp * (a * er - b * ei);", "pr += ww * dp * (a * er + b * ei);"),
+    "c_full_accumulates_wrong_part": ("acc[4 * l + 1] += qpi * dp[l];", "acc[4 * l + 1] += qpr * dp[l];"),
+    "c_full_sign_dropped": ("            if (m & 1) norm = -norm;\n            const int64_t k", "            const int64_t k"),
+    "c_m1_seed_sign": ("f = (mp < 0) ? 2.0 * c * s * s * s : -2.0 * c * c * c * s;",
+                       "f = (mp < 0) ? 2.0 * c * s * s * s : 2.0 * c * c * c * s;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(C_MUTANTS))
+def test_planted_spin_c_mistake_is_caught(oracle, tmp_path, name):
+    import shutil
+    import subprocess
+    from oracle import ref
+    old, new = C_MUTANTS[name]
+    odir = os.path.join(os.path.dirname(HERE), "oracle")
+    src = open(os.path.join(odir, "ptalm_ref.c")).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    shutil.copy(os.path.join(odir, "ptalm_ref.h"), tmp_path / "ptalm_ref.h")
+    (tmp_path / "ptalm_ref.c").write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(so),
+                    str(tmp_path / "ptalm_ref.c"), "-lm"], check=True)
+    with ref.use_library(str(so)):
+        assert not all(pin(ref) for pin in C_PINS), f"planted mistake {name!r} passed every C spin pin"
