@@ -16,6 +16,11 @@ computes sampled coefficients one by one over every point
   sampled entries of two weight vectors (<= 1e-4 of the l-rms) and weight vector
   0 against the FP64 path over all coefficients (global <= 1e-4).
 
+* the shear workload, 1e7 masked galaxies with shear at lmax 3072 in the bench's
+  launch configuration: sampled E and B coefficients against the C spin oracle
+  over every point, and the exact properties of the m = 0 column (E and B real,
+  bitwise) and of l < 2 (zero).
+
 Sampled entries are compared against the rms of the coefficients at their l,
 sqrt(C_l), as the bench does.
 """
@@ -142,3 +147,29 @@ def test_multi_weight_full_size(lib, oracle):
     g = np.linalg.norm(x - y) / np.linalg.norm(y)
     say(f"bf16x3 vs FP64, weight vector 0: global {g:.3e}")
     assert g <= 1e-4
+
+
+def test_shear_full_size(lib, oracle):
+    import torch
+    from paper_2312_12285_amd.synth import masked_galaxies, shear_components
+    lmax, n = 3072, 10_000_000
+    say("case: shear, 1e7 masked galaxies, lmax 3072")
+    g = masked_galaxies(n, seed_pos=61, seed_w=62)
+    g1, g2 = shear_components(n, seed=63)
+    d = dev(g.theta, g.phi, g.w, g1, g2)
+    e, b = lib.shear_alm_from_points(*d, lmax)
+    torch.cuda.synchronize()
+    pairs = [(2, 0), (2, 2), (3, 1), (100, 37), (1536, 700), (3072, 3072), (3072, 3000), (3071, 1)]
+    ls = [l for l, _ in pairs]
+    ms = [m for _, m in pairs]
+    we, wb = oracle.shear_eb_entries(g.theta, g.phi, g.w, g1, g2, ls, ms)
+    idx = [lib.alm_index(lmax, l, m) for l, m in pairs]
+    for name, got, want in (("E", e, we), ("B", b, wb)):
+        a = lib.as_complex(got).cpu().numpy()
+        cl = lib.cl_from_alm(got, lmax).cpu().numpy()
+        rel = np.abs(a[idx] - want) / np.sqrt(cl[ls])
+        say(f"shear {name}: sampled entries, max |err| / rms_l = {rel.max():.3e}")
+        assert rel.max() <= 1e-10
+        col0 = a[: lmax + 1]
+        assert np.all(col0.imag == 0.0)          # m = 0: both spins' sums cancel bitwise
+        assert np.all(a[[0, 1, lmax + 1]] == 0)  # l < 2
