@@ -79,15 +79,23 @@ WORKLOADS = {
 
 PROFILES = os.path.join(HERE, "profiles")
 # the kernel and the work plan that decides its launch (a change to either voids recorded traffic)
-KERNEL_SOURCES = [os.path.join(HERE, "paper_2312_12285_amd", "csrc", f) for f in ("alm_direct.hip", "api.hip")]
+CSRC = os.path.join(HERE, "paper_2312_12285_amd", "csrc")
+KERNEL_SOURCES = [os.path.join(CSRC, f) for f in ("alm_direct.hip", "wave_common.h")]
+PLAN_SOURCE = (os.path.join(CSRC, "api.hip"), "// Default kernel variant and decomposition.", "size_t align256(size_t b)")
 
 
 def kernel_source_hash():
+    """sha256 (first 16 hex digits) of the transform kernel's sources and of the part of
+    api.hip that picks its launch (defaults, slices, m-ranges)."""
     import hashlib
     h = hashlib.sha256()
     for path in KERNEL_SOURCES:
         with open(path, "rb") as f:
             h.update(f.read())
+    path, start, end = PLAN_SOURCE
+    with open(path) as f:
+        text = f.read()
+    h.update(text[text.index(start):text.index(end)].encode())
     return h.hexdigest()[:16]
 
 

@@ -142,7 +142,7 @@ def test_empty_tiny_and_arguments(lib):
     with pytest.raises(lib.PtalmError):
         lib.shear_alm_from_points(*a, 10, options=lib.opts(precision=lib.MIXED))
     with pytest.raises(lib.PtalmError):
-        lib.shear_alm_from_points(*a, 10, options=lib.opts(points_per_lane=7, l_block=8))
+        lib.shear_alm_from_points(*a, 10, options=lib.opts(points_per_lane=9, l_block=8))
     with pytest.raises(lib.PtalmError):
         lib.shear_alm_from_points(*a, 16384)
     with pytest.raises(ValueError):
