@@ -128,20 +128,24 @@ __global__ void scatter_kernel(const double *__restrict__ theta, const double *_
 constexpr int kBinM = 8;         // orders per binning wave
 constexpr int kBinThreads = 64;  // one wave per (interval, kBinM orders)
 constexpr int kBinVals = kBinM * 8;   // sums per wave: 4 basis functions x (re, im) per order
+constexpr int kBinPts = 2;       // points per lane per iteration
 
 // v[((m n_int) + j) * 4 + a] (complex) for the orders [kBinM p, kBinM (p + 1)) of interval j,
-// one wavefront each.  Wavefronts are numbered so that consecutive ones (the
-// passes over the same interval) land on the same XCD and reuse its L2 copy of
-// the interval's points.  Each lane sums a strided subset of the points (loading
-// its next point while it sums the current one); the 64 sums per lane are then
-// added across the wave.
+// one wavefront each.  Workgroups go to the 8 XCDs round robin (blockIdx mod 8);
+// interval j is given to XCD j mod 8 with all of its passes, so the passes
+// reuse that XCD's L2 copy of the interval's points, while neighbouring
+// intervals (whose point counts are alike: the mask and the sin(theta) area
+// factor vary slowly) spread over all XCDs and keep their loads balanced.  Each
+// lane sums a strided subset of the points (loading its next points while it
+// sums the current ones); the 64 sums per lane are then added across the wave.
 __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__restrict__ q, int64_t n_spline,
                                                           const int64_t *__restrict__ offsets, int n_int, int lmax,
-                                                          int n_pass, int64_t units_per_xcd,
-                                                          double2 *__restrict__ v) {
-    const int64_t L = (int64_t)(blockIdx.x & 7) * units_per_xcd + (blockIdx.x >> 3);
-    const int j = (int)(L / n_pass), pass = (int)(L % n_pass);
-    if (j >= n_int) return;
+                                                          int n_pass, double2 *__restrict__ v) {
+    const int64_t k = blockIdx.x >> 3;   // position in this XCD's sequence
+    const int64_t jj = (int64_t)(blockIdx.x & 7) + 8 * (k / n_pass);
+    const int pass = (int)(k % n_pass);
+    if (jj >= n_int) return;
+    const int j = (int)jj;
     const int m0 = pass * kBinM;
     const int lane = threadIdx.x;
     double acc[kBinM][8];
@@ -159,42 +163,68 @@ __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__res
     }
     // e^{-i m0 phi} from the reduced argument m0 phi / (2 pi) mod 1, taken exactly
     // (two-product of m0 and phi / (2 pi)), so sincospi sees a small argument.
-    // The next point's record is loaded (unconditionally, at a clamped index)
-    // while the current one is summed.
+    // Each lane takes kBinPts points per iteration (independent phase chains that
+    // the scheduler interleaves); the next iteration's records are loaded
+    // (unconditionally, at clamped indices) while the current ones are summed, and
+    // a point past the end of the interval contributes with weight 0.
     const double2 *rec = (const double2 *)q;
-    double2 nx[4];
+    double2 nx[kBinPts][4];
     auto fetch = [&](int64_t r) {
-        const int64_t rr = r < hi ? r : hi - 1;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) nx[a] = rec[rr * 4 + a];
+        for (int b = 0; b < kBinPts; ++b) {
+            const int64_t rb = r + b * kBinThreads;
+            const int64_t rr = rb < hi ? rb : hi - 1;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) nx[b][a] = rec[rr * 4 + a];
+        }
     };
     fetch(lo + lane);
-    for (int64_t r = lo + lane; r < hi; r += kBinThreads) {
-        const double2 c01 = nx[0], c23 = nx[1], pc = nx[2], s0 = nx[3];
-        fetch(r + kBinThreads);
-        const double q0 = c01.x, q1 = c01.y, q2 = c23.x, q3 = c23.y;
-        const double tph = pc.x, c1 = pc.y, s1 = s0.x;
-        const double p = (double)m0 * tph;
-        const double pe = fma((double)m0, tph, -p);
-        const double fr = (p - floor(p)) + pe;      // m0 phi / (2 pi) mod 1, within 2^-52
-        double sm, cm;
-        sincospi(2.0 * fr, &sm, &cm);
-        double zr = cm, zi = -sm;          // e^{-i m0 phi}
-        const double ur = c1, ui = -s1;    // e^{-i phi}
+    for (int64_t r = lo + lane; r < hi; r += kBinPts * kBinThreads) {
+        double q0[kBinPts], q1[kBinPts], q2[kBinPts], q3[kBinPts], zr[kBinPts], zi[kBinPts], ur[kBinPts],
+            ui[kBinPts];
+#pragma unroll
+        for (int b = 0; b < kBinPts; ++b) {
+            const double keep = (r + b * kBinThreads < hi) ? 1.0 : 0.0;
+            q0[b] = keep * nx[b][0].x;
+            q1[b] = keep * nx[b][0].y;
+            q2[b] = keep * nx[b][1].x;
+            q3[b] = keep * nx[b][1].y;
+            const double tph = nx[b][2].x;
+            ur[b] = nx[b][2].y;   // e^{-i phi}
+            ui[b] = -nx[b][3].x;
+            const double p = (double)m0 * tph;
+            const double pe = fma((double)m0, tph, -p);
+            const double fr = (p - floor(p)) + pe;      // m0 phi / (2 pi) mod 1, within 2^-52
+            double sm, cm;
+            sincospi(2.0 * fr, &sm, &cm);
+            zr[b] = cm;           // e^{-i m0 phi}
+            zi[b] = -sm;
+        }
+        fetch(r + kBinPts * kBinThreads);
 #pragma unroll
         for (int mm = 0; mm < kBinM; ++mm) {
-            acc[mm][0] = fma(q0, zr, acc[mm][0]);
-            acc[mm][1] = fma(q0, zi, acc[mm][1]);
-            acc[mm][2] = fma(q1, zr, acc[mm][2]);
-            acc[mm][3] = fma(q1, zi, acc[mm][3]);
-            acc[mm][4] = fma(q2, zr, acc[mm][4]);
-            acc[mm][5] = fma(q2, zi, acc[mm][5]);
-            acc[mm][6] = fma(q3, zr, acc[mm][6]);
-            acc[mm][7] = fma(q3, zi, acc[mm][7]);
-            const double nr = zr * ur - zi * ui;
-            zi = fma(zr, ui, zi * ur);
-            zr = nr;
+#pragma unroll
+            for (int b = 0; b < kBinPts; ++b) {
+                acc[mm][0] = fma(q0[b], zr[b], acc[mm][0]);
+                acc[mm][1] = fma(q0[b], zi[b], acc[mm][1]);
+                acc[mm][2] = fma(q1[b], zr[b], acc[mm][2]);
+                acc[mm][3] = fma(q1[b], zi[b], acc[mm][3]);
+                acc[mm][4] = fma(q2[b], zr[b], acc[mm][4]);
+                acc[mm][5] = fma(q2[b], zi[b], acc[mm][5]);
+                acc[mm][6] = fma(q3[b], zr[b], acc[mm][6]);
+                acc[mm][7] = fma(q3[b], zi[b], acc[mm][7]);
+                const double nr = zr[b] * ur[b] - zi[b] * ui[b];
+                zi[b] = fma(zr[b], ui[b], zi[b] * ur[b]);
+                zr[b] = nr;
+            }
         }
+        // Keep the prefetch one iteration ahead: without a use of the loaded
+        // registers here the compiler moves the loads into the next iteration,
+        // right before their use, and every point waits for L2.
+#pragma unroll
+        for (int b = 0; b < kBinPts; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) asm volatile("" : "+v"(nx[b][a].x), "+v"(nx[b][a].y));
     }
     // reduce-scatter butterflies over the wave, 64 values at a time: at each step
     // a lane keeps one half of its values and adds its partner's copy of that
@@ -450,10 +480,9 @@ hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
                                    double2 *wn, double *state, double *alm, hipStream_t stream) {
     double *sums = state;
-    const int64_t units = (int64_t)p.n_int * p.n_pass;
-    const int64_t per_xcd = (units + 7) / 8;
+    const int64_t per_xcd = (int64_t)((p.n_int + 7) / 8) * p.n_pass;   // units per XCD
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(per_xcd * 8)), dim3(kBinThreads), 0, stream, q, n_spline, offsets,
-                       p.n_int, lmax, p.n_pass, per_xcd, v);
+                       p.n_int, lmax, p.n_pass, v);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t total = (int64_t)(lmax + 1) * n_nodes;
