@@ -561,8 +561,11 @@ int ptalm_alm_from_points_spline(const double *theta, const double *phi, const d
         (e = mem.get((void **)&wn, sizeof(double) * plan.wn_doubles)) != hipSuccess ||
         (e = mem.get((void **)&state, sizeof(double) * plan.state_doubles)) != hipSuccess)
         return fail_hip(e, "hipMallocAsync");
+    const int *ranges;
+    int rc_r = get_ranges(lmax, plan.ns_ranges, &ranges);
+    if (rc_r != PTALM_OK) return rc_r;
     if ((e = ptalm::launch_spline_transform(plan, q, n_spline, offsets, xn, thn, n_nodes, lmax, (double2 *)v,
-                                            (double2 *)wn, state, alm, stream)) != hipSuccess)
+                                            (double2 *)wn, state, ranges, alm, stream)) != hipSuccess)
         return fail_hip(e, "spline transform kernels");
     if (n_polar > 0) {   // the polar caps by the exact sum, added to the interpolated part
         double *tmp;

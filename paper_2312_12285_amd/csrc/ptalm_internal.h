@@ -132,8 +132,23 @@ hipError_t launch_shot_noise(const double *w, int64_t n, const double *alpha, do
 
 // interpolated transform (spline.hip)
 struct SplinePlan {
-    int n_int = 0, n_pass = 0, n_chunks = 0;
+    int n_int = 0, n_pass = 0;
+    int ns_slices = 0, ns_ranges = 0;   // node sum: node slices x order ranges
+    int64_t ns_groups = 0;              // node groups of 64 KP
     size_t v_doubles = 0, wn_doubles = 0, state_doubles = 0;
+};
+// Arguments of the node-sum kernel (passed by value).
+struct NodeSumArgs {
+    const double *xn, *thn;
+    int n_nodes;
+    int lmax;
+    int n_ranges;
+    int n_slices;
+    int64_t groups;
+    const int *range_m;       // device, n_ranges+1
+    const double *coef;       // alpha table, coef_table_size(lmax)
+    const double2 *wn;        // node weights (V, F, G) per (m, node)
+    double *partial;          // n_slices * 4T doubles
 };
 SplinePlan spline_plan(int64_t n, int lmax, int n_nodes);
 hipError_t launch_spline_count(const double *theta, int64_t n, double theta_cut, double h, int n_nodes, double *xn,
@@ -144,7 +159,7 @@ hipError_t launch_spline_scatter(const double *theta, const double *phi, const d
                                  hipStream_t stream);
 hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
-                                   double2 *wn, double *state, double *alm, hipStream_t stream);
+                                   double2 *wn, double *state, const int *ranges, double *alm, hipStream_t stream);
 
 // Spin +-2 transform for shear: device tables per lmax, kernel arguments.
 struct SpinTables {

@@ -19,11 +19,12 @@
 //
 // Steps: count points per interval (polar points in an extra bucket), scan,
 // scatter into interval order with the spline weights w c_a precomputed,
-// binning (one workgroup per (interval, 16 orders)), node weights per (m, n),
-// and the node sum (one workgroup per m: the recurrence over l for 256 nodes
-// at a time writes a tile of y_l(x_n) to LDS, then threads own an l each and
-// sum over the nodes of the tile, so no cross-lane reduction is needed).
+// binning (one wavefront per (interval, 8 orders)), node weights per (m, n),
+// and the node sum as a direct sum over the nodes (the wavefront design of the
+// direct kernels: nodes in lanes, the recurrence over l in registers, four
+// sums per l reduced across lanes), then a_lm from its two sums per l.
 #include "ptalm_internal.h"
+#include "wave_common.h"
 
 namespace ptalm {
 
@@ -290,140 +291,255 @@ __global__ void node_weights_kernel(const double2 *__restrict__ v, const double 
     }
 }
 
-constexpr int kNodeChunk = 256;   // nodes per tile (one per thread in the recurrence phase)
-constexpr int kNodeLB = 16;       // degrees per tile
-constexpr int kTilePitch = kNodeChunk + 1;
-constexpr int kNodeParts = 256 / kNodeLB;   // node groups summed separately in phase 2
-
-// exact 2^e for the range used here, 0 below the double range
-__device__ inline double pow2i(int e) { return e < -1074 ? 0.0 : ldexp(1.0, e); }
-
-// One workgroup per order m.  Chunks of 256 nodes in order; per chunk each
-// thread carries its node's recurrence in registers (a scaled pair with a
-// binary exponent) through all degrees, 16 at a time: it writes y_l(x_n) of
-// the block to an LDS tile, then thread (l, part) sums its degree over 16
-// nodes of the tile against the node weights, the 16 parts are added in order
-// and the block's sums are accumulated over the chunks (in chunk order) in
-// sums[idx(l, m)][6] = (A, F, G) as complex pairs.  Finally
-// a_lm = A_l - l F_l + d_l G_{l-1}.
-__global__ __launch_bounds__(256) void node_sum_kernel(const double *__restrict__ xn, const double *__restrict__ thn,
-                                                      int n_nodes, int lmax, const double2 *__restrict__ wn,
-                                                      double *__restrict__ sums, double *__restrict__ alm) {
-    __shared__ double tile[kNodeLB * kTilePitch];
-    __shared__ double2 wt[kNodeChunk * 3];
-    __shared__ double part[kNodeParts][kNodeLB][6];
-    __shared__ double coef_a[kNodeLB], coef_b[kNodeLB];
-    const int m = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int n_chunks = (n_nodes + kNodeChunk - 1) / kNodeChunk;
-    const int lanel = tid % kNodeLB, partid = tid / kNodeLB;   // 16 degrees x 16 parts
-    // seed factor (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)); y_mm = factor s^m
+constexpr int kNsKP = 4;            // node sum: nodes per lane
+constexpr int kNsLB = 8;            // node sum: degrees per register block
+constexpr int kNsMaxSlices = 8;     // node sum: node slices (partial columns)
+constexpr int kNsItems = 16384;     // node sum: target (slice, order range) items
+// Node-sum tables, one thread per order m.  With y_l = c_m s^m kappa_l E_l
+// (c_m = (-1)^m sqrt((2m+1)/4pi prod_{k<=m} (2k-1)/(2k)), the sectoral seed of
+// App. A.1), kappa_m = kappa_{m+1} = 1 and kappa_l = b_l kappa_{l-2}, the
+// three-term recurrence y_l = a_l x y_{l-1} - b_l y_{l-2} becomes
+// E_l = alpha_l x E_{l-1} - E_{l-2} with alpha_l = a_l kappa_{l-1} / kappa_l.
+// alpha at coef[segment(m) + l - m] (0 at l = m, where the kernel's general step
+// turns its start state (0, -1) into E_m = 1; zero past lmax through the padding),
+// scale c_m kappa_l at sig[column_start(m) + l - m].
+__global__ void node_tables_kernel(int lmax, double *coef, double *sig) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m > lmax) return;
     double cm2 = (2.0 * m + 1.0) * kInv4Pi;
     for (int k = 1; k <= m; ++k) cm2 *= (2.0 * k - 1.0) / (2.0 * k);
     const double cm = sqrt(cm2) * ((m & 1) ? -1.0 : 1.0);
-    for (int c = 0; c < n_chunks; ++c) {
-        const int n = c * kNodeChunk + tid;
-        const bool live = n < n_nodes;
-        double vp = 0.0, vc = 0.0, f = 0.0, x = 0.0;
-        int E = 0;
-        if (live) {   // s^m as mantissa x 2^E by binary powering with renormalisation
-            int es;
-            double b = frexp(sin(thn[n]), &es), r = 1.0;
-            int e = 0, eb = es;
-            for (int k = m; k > 0; k >>= 1) {
-                if (k & 1) {
-                    int t;
-                    r = frexp(r * b, &t);
-                    e += t + eb;
-                }
-                int t2;
-                b = frexp(b * b, &t2);
-                eb = 2 * eb + t2;
-            }
-            vc = cm * r;
-            E = e;
-            f = pow2i(E);
-            x = xn[n];
+    double *seg = coef + coef_segment(lmax, m);
+    const int64_t col = column_start(lmax, m);
+    const int jmax = lmax - m;
+    for (int j = 0; j <= jmax + kCoefPad; ++j) seg[j] = 0.0;
+    sig[col] = cm;
+    double kap2 = 1.0, kap1 = 1.0;   // kappa_{l-2}, kappa_{l-1}
+    for (int l = m + 1; l <= lmax; ++l) {
+        const double ll = l, mm = m;
+        const double a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+        double kap;
+        if (l == m + 1) {
+            kap = 1.0;
+        } else {
+            const double b = sqrt((2.0 * ll + 1.0) * ((ll - 1.0) * (ll - 1.0) - mm * mm) /
+                                  ((2.0 * ll - 3.0) * (ll * ll - mm * mm)));
+            kap = b * kap2;
         }
-        __syncthreads();   // the previous chunk's last reads of wt are done
-        for (int k = 0; k < 3; ++k)
-            wt[tid * 3 + k] = live ? wn[((int64_t)m * n_nodes + n) * 3 + k] : make_double2(0.0, 0.0);
-        for (int l0 = m; l0 <= lmax; l0 += kNodeLB) {
-            const int nl = lmax + 1 - l0 < kNodeLB ? lmax + 1 - l0 : kNodeLB;
-            double g6[6] = {0, 0, 0, 0, 0, 0};
-            if (tid < nl) {
-                const int l = l0 + tid;
-                if (c > 0) {   // running sums of the earlier chunks (loaded early)
-                    const double *src = sums + hp_index(lmax, l, m) * 6;
-                    for (int i = 0; i < 6; ++i) g6[i] = src[i];
+        seg[l - m] = a * kap1 / kap;
+        sig[col + (l - m)] = cm * kap;
+        kap2 = kap1;
+        kap1 = kap;
+    }
+}
+
+// The node sum as a direct sum over nodes: for order m and degree l,
+//     P_l = sum_n s_n^m (V_n - l F_n) E_l(x_n),   Q_l = sum_n s_n^m G_n E_{l-1}(x_n),
+// and a_lm = c_m kappa_l P_l + d_l c_m kappa_{l-1} Q_l (= A_l - l F_l + d_l G_{l-1}
+// with the sums of the node weights against y_l).  Work decomposition of the
+// direct kernels: groups of 64*KP nodes, S node slices, R order ranges, one
+// wavefront per (slice, range); s^m as a mantissa with a binary exponent
+// advanced by s per order; the chain rescaled every 64 l; the four sums per l
+// reduced across lanes in a fixed order into the slice's partial column.
+// Per (node, l, m): 8 FP64 operations (chain 2, V - l F 2, P 2, Q 2).
+template <int KP, int LB>
+__global__ __launch_bounds__(64) void node_sum_wave_kernel(NodeSumArgs a) {
+    static_assert(LB % 2 == 0 && 64 % (4 * LB) == 0, "4*LB must divide 64");
+    constexpr int V = 4 * LB;
+    using R = Red<V, 1>;
+    constexpr int P = R::P;
+    constexpr int RESCALE_EVERY = ChainRange<double>::every_l / LB;
+    constexpr double kAbove = ChainRange<double>::above;
+
+    __shared__ double red[2 * R::BUF];
+
+    const int lane = threadIdx.x;
+    const int lmax = a.lmax;
+    const int r = blockIdx.x % a.n_ranges;
+    const int s = blockIdx.x / a.n_ranges;
+    const int m_a = __builtin_amdgcn_readfirstlane(a.range_m[r]);
+    const int m_b = __builtin_amdgcn_readfirstlane(a.range_m[r + 1]);
+    const const_ptr<double> coef = (const_ptr<double>)(const void *)a.coef;
+    const int64_t g_a = (int64_t)s * a.groups / a.n_slices;
+    const int64_t g_b = (int64_t)(s + 1) * a.groups / a.n_slices;
+    double *part = a.partial + (int64_t)s * 4 * tri_size(lmax);
+    const int v = lane / P;
+    const int h = lane % P;
+
+    for (int64_t g = g_a; g < g_b; ++g) {
+        const bool first = (g == g_a);
+        double x[KP], sn[KP], Z[KP];
+        int Ze[KP];
+        bool live[KP];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) {
+            const int64_t n = g * (64 * KP) + t * 64 + lane;
+            live[t] = n < a.n_nodes;
+            x[t] = live[t] ? a.xn[n] : 0.0;
+            sn[t] = live[t] ? sin(a.thn[n]) : 0.0;
+            // s^{m_a} by binary powering with renormalisation
+            int eb = 0, e = 0, tt;
+            double b = frexp(sn[t], &eb), rr = 1.0;
+            for (int k = m_a; k > 0; k >>= 1) {
+                if (k & 1) {
+                    rr = frexp(rr * b, &tt);
+                    e += tt + eb;
                 }
-                double a = 0.0, bb = 0.0;
-                if (l > m) {
-                    const double ll = (double)l, mm = (double)m;
-                    a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
-                    bb = l > m + 1 ? sqrt((2.0 * ll + 1.0) * ((ll - 1.0) * (ll - 1.0) - mm * mm) /
-                                          ((2.0 * ll - 3.0) * (ll * ll - mm * mm)))
-                                   : 0.0;
-                }
-                coef_a[tid] = a;
-                coef_b[tid] = bb;
+                b = frexp(b * b, &tt);
+                eb = 2 * eb + tt;
             }
-            __syncthreads();   // coefficients ready; tile free
-            for (int k = 0; k < nl; ++k) {
-                if (l0 + k > m) {
-                    const double nv = fma(coef_a[k] * x, vc, -coef_b[k] * vp);
-                    vp = vc;
-                    vc = nv;
+            Z[t] = live[t] ? rr : 0.0;
+            Ze[t] = e;
+        }
+        for (int m = m_a; m < m_b; ++m) {
+            const int L = lmax - m + 1;
+            const const_ptr<double> cm = coef + coef_segment(lmax, m);
+            double *pm = part + 4 * column_start(lmax, m);
+            double E[KP], Ep[KP], WVr[KP], WVi[KP], WFr[KP], WFi[KP], WGr[KP], WGi[KP];
+            int q[KP];
+#pragma unroll
+            for (int t = 0; t < KP; ++t) {
+                const int64_t n = g * (64 * KP) + t * 64 + lane;
+                double2 wv = make_double2(0.0, 0.0), wf = wv, wg = wv;
+                if (live[t]) {
+                    const double2 *src = a.wn + ((int64_t)m * a.n_nodes + n) * 3;
+                    wv = src[0];
+                    wf = src[1];
+                    wg = src[2];
                 }
-                tile[k * kTilePitch + tid] = live ? vc * f : 0.0;
-                if ((k & 7) == 7 && fabs(vc) > 0x1p600) {
-                    vc *= 0x1p-600;
-                    vp *= 0x1p-600;
-                    E += 600;
-                    f = pow2i(E);
+                q[t] = Ze[t];
+                const double z = ldexp_t(Z[t], q[t]);
+                WVr[t] = z * wv.x;
+                WVi[t] = z * wv.y;
+                WFr[t] = z * wf.x;
+                WFi[t] = z * wf.y;
+                WGr[t] = z * wg.x;
+                WGi[t] = z * wg.y;
+                E[t] = 0.0;
+                Ep[t] = -1.0;
+            }
+            bool pending = false;
+            bool p_owner = false;
+            double *p_dst = pm;
+            double p_prev = 0.0;
+            int cur = 0;
+            int blk = 0;
+            for (int jb = 0; jb < L; jb += LB, ++blk) {
+                const bool owner = (h == 0) && (jb + (v >> 2) < L);
+                double *dst = pm + 4 * jb + v;
+                double prev = 0.0;
+                if (owner && !first) prev = *dst;
+                double al[LB];
+#pragma unroll
+                for (int k = 0; k < LB; ++k) al[k] = cm[jb + k];
+                double vals[V];
+#pragma unroll
+                for (int k = 0; k < LB; ++k) {
+                    const double ml = -(double)(m + jb + k);
+                    double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+#pragma unroll
+                    for (int t = 0; t < KP; ++t) {
+                        const double en = fma(al[k] * x[t], E[t], -Ep[t]);
+                        const double tr = fma(ml, WFr[t], WVr[t]);
+                        const double ti = fma(ml, WFi[t], WVi[t]);
+                        pr = fma(tr, en, pr);
+                        pi = fma(ti, en, pi);
+                        qr = fma(WGr[t], E[t], qr);
+                        qi = fma(WGi[t], E[t], qi);
+                        Ep[t] = E[t];
+                        E[t] = en;
+                    }
+                    vals[4 * k] = pr;
+                    vals[4 * k + 1] = pi;
+                    vals[4 * k + 2] = qr;
+                    vals[4 * k + 3] = qi;
+                }
+                if (pending) {
+                    wave_lds_sync();
+                    const double sum = reduce_finish<double, V, 1>(red + (cur ^ 1) * R::BUF, v, h);
+                    if (p_owner) *p_dst = p_prev + sum;
+                }
+                reduce_write<double, V, 1>(red + cur * R::BUF, vals, lane);
+                pending = true;
+                p_owner = owner;
+                p_dst = dst;
+                p_prev = prev;
+                cur ^= 1;
+
+                if ((blk % RESCALE_EVERY) == RESCALE_EVERY - 1) {
+                    bool big = false;
+#pragma unroll
+                    for (int t = 0; t < KP; ++t) big |= fmax(fabs(E[t]), fabs(Ep[t])) > kAbove;
+                    if (__any(big)) {
+#pragma unroll
+                        for (int t = 0; t < KP; ++t) {
+                            const double mx = fmax(fabs(E[t]), fabs(Ep[t]));
+                            const int e = (mx > kAbove) ? frexp_exp_t(mx) : 0;
+                            E[t] = ldexp_t(E[t], -e);
+                            Ep[t] = ldexp_t(Ep[t], -e);
+                            q[t] += e;
+                            const int64_t n = g * (64 * KP) + t * 64 + lane;
+                            double2 wv = make_double2(0.0, 0.0), wf = wv, wg = wv;
+                            if (live[t]) {   // the weights again (re-read: they are not kept)
+                                const double2 *src = a.wn + ((int64_t)m * a.n_nodes + n) * 3;
+                                wv = src[0];
+                                wf = src[1];
+                                wg = src[2];
+                            }
+                            const double z = ldexp_t(Z[t], q[t]);
+                            WVr[t] = z * wv.x;
+                            WVi[t] = z * wv.y;
+                            WFr[t] = z * wf.x;
+                            WFi[t] = z * wf.y;
+                            WGr[t] = z * wg.x;
+                            WGi[t] = z * wg.y;
+                        }
+                    }
                 }
             }
-            __syncthreads();
-            double acc[6] = {0, 0, 0, 0, 0, 0};
-            if (lanel < nl) {
-#pragma unroll 4
-                for (int q = 0; q < kNodeChunk / kNodeParts; ++q) {
-                    const int nn = partid * (kNodeChunk / kNodeParts) + q;
-                    const double y = tile[lanel * kTilePitch + nn];
-                    const double2 a = wt[nn * 3], b = wt[nn * 3 + 1], g = wt[nn * 3 + 2];
-                    acc[0] = fma(a.x, y, acc[0]);
-                    acc[1] = fma(a.y, y, acc[1]);
-                    acc[2] = fma(b.x, y, acc[2]);
-                    acc[3] = fma(b.y, y, acc[3]);
-                    acc[4] = fma(g.x, y, acc[4]);
-                    acc[5] = fma(g.y, y, acc[5]);
-                }
+            if (pending) {
+                wave_lds_sync();
+                const double sum = reduce_finish<double, V, 1>(red + (cur ^ 1) * R::BUF, v, h);
+                if (p_owner) *p_dst = p_prev + sum;
+                wave_lds_sync();
             }
-            for (int k = 0; k < 6; ++k) part[partid][lanel][k] = acc[k];
-            __syncthreads();
-            if (tid < nl) {   // degree l0 + tid: the parts in order, then the chunk total
-                double s6[6] = {0, 0, 0, 0, 0, 0};
-                for (int p = 0; p < kNodeParts; ++p)
-                    for (int i = 0; i < 6; ++i) s6[i] += part[p][tid][i];
-                double *dst = sums + hp_index(lmax, l0 + tid, m) * 6;
-                for (int i = 0; i < 6; ++i) dst[i] = g6[i] + s6[i];
+            // next order: Z <- Z s
+#pragma unroll
+            for (int t = 0; t < KP; ++t) {
+                int tt;
+                Z[t] = frexp(Z[t] * sn[t], &tt);
+                Ze[t] += tt;
             }
         }
     }
-    __syncthreads();   // every chunk's sums are visible to the workgroup
-    for (int l = m + tid; l <= lmax; l += blockDim.x) {
-        const double *s6 = sums + hp_index(lmax, l, m) * 6;
-        double re = s6[0] - l * s6[2], im = s6[1] - l * s6[3];
-        if (l > m) {
-            const double ll = (double)l, mm = (double)m;
-            const double d = sqrt((2.0 * ll + 1.0) / (2.0 * ll - 1.0) * (ll * ll - mm * mm));
-            const double *gp = sums + hp_index(lmax, l - 1, m) * 6;
-            re = fma(d, gp[4], re);
-            im = fma(d, gp[5], im);
+}
+
+// a_lm = sig_l P_l + d_l sig_{l-1} Q_l with the slice sums in slice order; one
+// workgroup per order m.
+__global__ void node_finish_kernel(const double *__restrict__ partial, int n_slices, const double *__restrict__ sig,
+                                   int lmax, double *__restrict__ alm) {
+    const int m = blockIdx.x;
+    const int64_t T = tri_size(lmax);
+    const int64_t col = column_start(lmax, m);
+    for (int l = m + threadIdx.x; l <= lmax; l += blockDim.x) {
+        const int64_t k = col + (l - m);
+        double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+        for (int s = 0; s < n_slices; ++s) {
+            const double4 v = reinterpret_cast<const double4 *>(partial + (int64_t)s * 4 * T)[k];
+            pr += v.x;
+            pi += v.y;
+            qr += v.z;
+            qi += v.w;
         }
-        const int64_t idx = hp_index(lmax, l, m);
-        alm[2 * idx] = re;
-        alm[2 * idx + 1] = im;
+        double re = sig[k] * pr, im = sig[k] * pi;
+        if (l > m) {
+            const double ll = l, mm = m;
+            const double d = sqrt((2.0 * ll + 1.0) / (2.0 * ll - 1.0) * (ll * ll - mm * mm)) * sig[k - 1];
+            re = fma(d, qr, re);
+            im = fma(d, qi, im);
+        }
+        alm[2 * k] = re;
+        alm[2 * k + 1] = im;
     }
 }
 
@@ -439,10 +555,15 @@ SplinePlan spline_plan(int64_t n, int lmax, int n_nodes) {
     SplinePlan p;
     p.n_int = n_nodes - 1;
     p.n_pass = (lmax + kBinM) / kBinM;
-    p.n_chunks = (n_nodes + kNodeChunk - 1) / kNodeChunk;
     p.v_doubles = (size_t)(lmax + 1) * p.n_int * 8;
     p.wn_doubles = (size_t)(lmax + 1) * n_nodes * 6;
-    p.state_doubles = (size_t)tri_size(lmax) * 6;   // node sums (A, F, G) per (l, m)
+    p.ns_groups = (n_nodes + 64 * kNsKP - 1) / (64 * kNsKP);
+    p.ns_slices = (int)(p.ns_groups < kNsMaxSlices ? p.ns_groups : kNsMaxSlices);
+    const int want = kNsItems / p.ns_slices;
+    p.ns_ranges = want < lmax + 1 ? (want > 0 ? want : 1) : lmax + 1;
+    // node-sum partials (4 per (l, m) and slice), alpha table, scale table
+    p.state_doubles = (size_t)p.ns_slices * 4 * (size_t)tri_size(lmax) + (size_t)coef_table_size(lmax) +
+                      (size_t)tri_size(lmax);
     (void)n;
     return p;
 }
@@ -478,8 +599,10 @@ hipError_t launch_spline_scatter(const double *theta, const double *phi, const d
 
 hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
-                                   double2 *wn, double *state, double *alm, hipStream_t stream) {
-    double *sums = state;
+                                   double2 *wn, double *state, const int *ranges, double *alm, hipStream_t stream) {
+    double *partial = state;
+    double *coef = partial + (size_t)p.ns_slices * 4 * (size_t)tri_size(lmax);
+    double *sig = coef + coef_table_size(lmax);
     const int64_t per_xcd = (int64_t)((p.n_int + 7) / 8) * p.n_pass;   // units per XCD
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(per_xcd * 8)), dim3(kBinThreads), 0, stream, q, n_spline, offsets,
                        p.n_int, lmax, p.n_pass, v);
@@ -489,8 +612,25 @@ hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t
     hipLaunchKernelGGL(node_weights_kernel, dim3(grid_for(total, 256, 65536)), dim3(256), 0, stream,
                        (const double2 *)v, xn, n_nodes, lmax, wn);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(node_sum_kernel, dim3(lmax + 1), dim3(256), 0, stream, xn, thn, n_nodes, lmax,
-                       (const double2 *)wn, sums, alm);
+    hipLaunchKernelGGL(node_tables_kernel, dim3((lmax + 64) / 64), dim3(64), 0, stream, lmax, coef, sig);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    NodeSumArgs a;
+    a.xn = xn;
+    a.thn = thn;
+    a.n_nodes = n_nodes;
+    a.lmax = lmax;
+    a.n_ranges = p.ns_ranges;
+    a.n_slices = p.ns_slices;
+    a.groups = p.ns_groups;
+    a.range_m = ranges;
+    a.coef = coef;
+    a.wn = wn;
+    a.partial = partial;
+    hipLaunchKernelGGL((node_sum_wave_kernel<kNsKP, kNsLB>), dim3((unsigned)(p.ns_ranges * p.ns_slices)), dim3(64), 0,
+                       stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(node_finish_kernel, dim3(lmax + 1), dim3(256), 0, stream, (const double *)partial, p.ns_slices,
+                       (const double *)sig, lmax, alm);
     return hipGetLastError();
 }
 
