@@ -23,6 +23,8 @@
 // and the node sum as a direct sum over the nodes (the wavefront design of the
 // direct kernels: nodes in lanes, the recurrence over l in registers, four
 // sums per l reduced across lanes), then a_lm from its two sums per l.
+#include <type_traits>
+
 #include "ptalm_internal.h"
 #include "wave_common.h"
 
@@ -179,20 +181,21 @@ __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__res
             for (int a = 0; a < 4; ++a) nx[b][a] = rec[rr * 4 + a];
         }
     };
-    fetch(lo + lane);
-    for (int64_t r = lo + lane; r < hi; r += kBinPts * kBinThreads) {
-        double q0[kBinPts], q1[kBinPts], q2[kBinPts], q3[kBinPts], zr[kBinPts], zi[kBinPts], ur[kBinPts],
-            ui[kBinPts];
+    // Per point and pass: e^{-i m0 phi} and e^{-i (m0-1) phi}, then the orders
+    // m0 .. m0+7 by the two-term recurrence z_{m+1} = 2 cos(phi) z_m - z_{m-1}
+    // (two FMAs per order).  Iterations whose points all lie in the interval
+    // skip the masking; the last one (per lane) gives points past the end weight 0.
+    auto body = [&](int64_t r, auto tail) {
+        double q0[kBinPts], q1[kBinPts], q2[kBinPts], q3[kBinPts], zr[kBinPts], zi[kBinPts], pr[kBinPts],
+            pi[kBinPts], tc[kBinPts];
 #pragma unroll
         for (int b = 0; b < kBinPts; ++b) {
-            const double keep = (r + b * kBinThreads < hi) ? 1.0 : 0.0;
-            q0[b] = keep * nx[b][0].x;
-            q1[b] = keep * nx[b][0].y;
-            q2[b] = keep * nx[b][1].x;
-            q3[b] = keep * nx[b][1].y;
-            const double tph = nx[b][2].x;
-            ur[b] = nx[b][2].y;   // e^{-i phi}
-            ui[b] = -nx[b][3].x;
+            const double keep = (!decltype(tail)::value || r + b * kBinThreads < hi) ? 1.0 : 0.0;
+            q0[b] = decltype(tail)::value ? keep * nx[b][0].x : nx[b][0].x;
+            q1[b] = decltype(tail)::value ? keep * nx[b][0].y : nx[b][0].y;
+            q2[b] = decltype(tail)::value ? keep * nx[b][1].x : nx[b][1].x;
+            q3[b] = decltype(tail)::value ? keep * nx[b][1].y : nx[b][1].y;
+            const double tph = nx[b][2].x, c1 = nx[b][2].y, s1 = nx[b][3].x;
             const double p = (double)m0 * tph;
             const double pe = fma((double)m0, tph, -p);
             const double fr = (p - floor(p)) + pe;      // m0 phi / (2 pi) mod 1, within 2^-52
@@ -200,6 +203,10 @@ __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__res
             sincospi(2.0 * fr, &sm, &cm);
             zr[b] = cm;           // e^{-i m0 phi}
             zi[b] = -sm;
+            // e^{-i (m0 - 1) phi} = (cm - i sm)(c1 + i s1)
+            pr[b] = fma(cm, c1, sm * s1);
+            pi[b] = fma(cm, s1, -sm * c1);
+            tc[b] = 2.0 * c1;
         }
         fetch(r + kBinPts * kBinThreads);
 #pragma unroll
@@ -214,9 +221,14 @@ __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__res
                 acc[mm][5] = fma(q2[b], zi[b], acc[mm][5]);
                 acc[mm][6] = fma(q3[b], zr[b], acc[mm][6]);
                 acc[mm][7] = fma(q3[b], zi[b], acc[mm][7]);
-                const double nr = zr[b] * ur[b] - zi[b] * ui[b];
-                zi[b] = fma(zr[b], ui[b], zi[b] * ur[b]);
-                zr[b] = nr;
+                if (mm + 1 < kBinM) {
+                    const double nr = fma(tc[b], zr[b], -pr[b]);
+                    const double ni = fma(tc[b], zi[b], -pi[b]);
+                    pr[b] = zr[b];
+                    pi[b] = zi[b];
+                    zr[b] = nr;
+                    zi[b] = ni;
+                }
             }
         }
         // Keep the prefetch one iteration ahead: without a use of the loaded
@@ -226,7 +238,11 @@ __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__res
         for (int b = 0; b < kBinPts; ++b)
 #pragma unroll
             for (int a = 0; a < 4; ++a) asm volatile("" : "+v"(nx[b][a].x), "+v"(nx[b][a].y));
-    }
+    };
+    fetch(lo + lane);
+    int64_t r = lo + lane;
+    for (; r + (kBinPts - 1) * kBinThreads < hi; r += kBinPts * kBinThreads) body(r, std::false_type{});
+    if (r < hi) body(r, std::true_type{});
     // reduce-scatter butterflies over the wave, 64 values at a time: at each step
     // a lane keeps one half of its values and adds its partner's copy of that
     // half; lane k ends with the total of value 64 g + k (= 8 mm + c), always
