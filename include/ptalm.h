@@ -211,13 +211,17 @@ int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, in
  * a_lm = sum_j [v_j0 y(x_j) + v_j1 dx_j y'(x_j) + v_j2 y(x_{j+1}) + v_j3 dx_j y'(x_{j+1})]
  * with y' from the derivative relation of App. A.1.  Approximate: the error
  * falls like (l h)^4 with the node spacing h in theta.  FP64 throughout.
- * Allocates stream-ordered scratch (about 40 B per point plus
- * (lmax+1) x n_nodes x 112 B) and synchronizes `stream` once (to size the
- * polar part).  Points inside one interval are summed in the order a scatter
- * with atomic counters placed them, so repeated calls can differ in the last
- * bits.  PTALM_EINVAL on bad sizes or pointers. */
+ * Allocates stream-ordered scratch (about 64 B per point, plus
+ * (lmax+1) x n_nodes x 112 B, plus about 270 B per (l, m)) and synchronizes
+ * `stream` once (to size the polar part).  Points inside one interval are
+ * summed in the order a scatter with atomic counters placed them, so repeated
+ * calls can differ in the last bits.  opts: NULL, or opts->timing != 0 to
+ * record HIP events around the binning kernel (the dominant one) on `stream`,
+ * read with ptalm_last_timing(); the other fields are not used.
+ * PTALM_EINVAL on bad sizes or pointers. */
 int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
-                                 int n_nodes, double theta_cut, double *alm, void *stream);
+                                 int n_nodes, double theta_cut, double *alm, const ptalm_opts *opts,
+                                 void *stream);
 
 /*
  * Spin-weighted transform for shear (spin +-2 harmonics in place of Y_lm, the
@@ -251,7 +255,8 @@ size_t ptalm_shear_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts);
 /* Device time of the transform kernel(s) of the last ptalm_alm_from_points_ex
  * or ptalm_shear_alm_from_points call made on this thread with opts->timing
  * set: from just before the first transform kernel to just after the last
- * one, on that call's stream.  Blocks
+ * one, on that call's stream (for ptalm_alm_from_points_spline: its binning
+ * kernel).  Blocks
  * until that work has finished.  PTALM_EINVAL if no timed call was made.
  * Host only. */
 int ptalm_last_timing(double *transform_ms);

@@ -514,7 +514,7 @@ struct AsyncAllocs {
 }  // namespace
 
 int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
-                                 int n_nodes, double theta_cut, double *alm, void *stream_) {
+                                 int n_nodes, double theta_cut, double *alm, const ptalm_opts *opts, void *stream_) {
     g_error.clear();
     if (n < 0) return fail(PTALM_EINVAL, "n < 0");
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
@@ -564,9 +564,18 @@ int ptalm_alm_from_points_spline(const double *theta, const double *phi, const d
     const int *ranges;
     int rc_r = get_ranges(lmax, plan.ns_ranges, &ranges);
     if (rc_r != PTALM_OK) return rc_r;
+    const bool timed = opts != nullptr && opts->timing != 0;
+    if (timed) {
+        g_timing.valid = false;
+        if (!g_timing.start && (e = hipEventCreate(&g_timing.start)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+        if (!g_timing.stop && (e = hipEventCreate(&g_timing.stop)) != hipSuccess) return fail_hip(e, "hipEventCreate");
+    }
     if ((e = ptalm::launch_spline_transform(plan, q, n_spline, offsets, xn, thn, n_nodes, lmax, (double2 *)v,
-                                            (double2 *)wn, state, ranges, alm, stream)) != hipSuccess)
+                                            (double2 *)wn, state, ranges, alm, stream,
+                                            timed ? g_timing.start : nullptr, timed ? g_timing.stop : nullptr)) !=
+        hipSuccess)
         return fail_hip(e, "spline transform kernels");
+    if (timed) g_timing.valid = true;
     if (n_polar > 0) {   // the polar caps by the exact sum, added to the interpolated part
         double *tmp;
         if ((e = mem.get((void **)&tmp, sizeof(double) * 2 * (size_t)T)) != hipSuccess)

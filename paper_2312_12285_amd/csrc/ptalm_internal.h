@@ -159,7 +159,8 @@ hipError_t launch_spline_scatter(const double *theta, const double *phi, const d
                                  hipStream_t stream);
 hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
-                                   double2 *wn, double *state, const int *ranges, double *alm, hipStream_t stream);
+                                   double2 *wn, double *state, const int *ranges, double *alm, hipStream_t stream,
+                                   hipEvent_t bin_start = nullptr, hipEvent_t bin_stop = nullptr);
 
 // Spin +-2 transform for shear: device tables per lmax, kernel arguments.
 struct SpinTables {

@@ -615,15 +615,18 @@ hipError_t launch_spline_scatter(const double *theta, const double *phi, const d
 
 hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
-                                   double2 *wn, double *state, const int *ranges, double *alm, hipStream_t stream) {
+                                   double2 *wn, double *state, const int *ranges, double *alm, hipStream_t stream,
+                                   hipEvent_t bin_start, hipEvent_t bin_stop) {
     double *partial = state;
     double *coef = partial + (size_t)p.ns_slices * 4 * (size_t)tri_size(lmax);
     double *sig = coef + coef_table_size(lmax);
     const int64_t per_xcd = (int64_t)((p.n_int + 7) / 8) * p.n_pass;   // units per XCD
+    hipError_t e;
+    if (bin_start && (e = hipEventRecord(bin_start, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(per_xcd * 8)), dim3(kBinThreads), 0, stream, q, n_spline, offsets,
                        p.n_int, lmax, p.n_pass, v);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (bin_stop && (e = hipEventRecord(bin_stop, stream)) != hipSuccess) return e;
     const int64_t total = (int64_t)(lmax + 1) * n_nodes;
     hipLaunchKernelGGL(node_weights_kernel, dim3(grid_for(total, 256, 65536)), dim3(256), 0, stream,
                        (const double2 *)v, xn, n_nodes, lmax, wn);

@@ -64,7 +64,7 @@ _bp_count = _sig("ptalm_bandpower_count", ctypes.c_int, [ctypes.c_int, ctypes.c_
 _bandpowers = _sig("ptalm_bandpowers", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                      ctypes.c_int, ctypes.c_int, _vp, _vp, _vp])
 _alm_spline = _sig("ptalm_alm_from_points_spline", ctypes.c_int,
-                   [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, _vp])
+                   [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(Opts), _vp])
 _shear = _sig("ptalm_shear_alm_from_points", ctypes.c_int,
               [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.c_int, _vp, _vp, ctypes.POINTER(Opts), _vp])
 _shear_ws = _sig("ptalm_shear_workspace_bytes", ctypes.c_size_t, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
@@ -267,7 +267,8 @@ def bandpowers(cl_hat, M, lmax: int, delta_l: int, lmin: int = 0, mode: int = 0,
     return cb, window
 
 
-def alm_from_points_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float, out=None, stream=None):
+def alm_from_points_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float, out=None,
+                           options: Opts | None = None, stream=None):
     """a_lm by the interpolated transform of App. A.2 (cubic Hermite splines on n_nodes nodes
     uniform in theta over [theta_cut, pi - theta_cut]; the polar caps by the exact sum).
     Same layout as alm_from_points with one weight vector."""
@@ -283,7 +284,7 @@ def alm_from_points_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: fl
         if out.numel() != 2 * T:
             raise ValueError("out has the wrong size")
     _check(_alm_spline(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, n_nodes, float(theta_cut), _ptr(out),
-                       _stream(stream)))
+                       None if options is None else ctypes.byref(options), _stream(stream)))
     return out
 
 

@@ -94,3 +94,16 @@ def test_empty_and_argument_checks(lib):
     for nodes, cut in ((1, 0.1), (16, 0.0), (16, math.pi / 2), (70000, 0.1)):
         with pytest.raises(lib.PtalmError):
             lib.alm_from_points_spline(x, x, x, 10, nodes, cut)
+
+
+def test_timing_option_times_the_binning_kernel(lib):
+    """opts.timing records events around the binning kernel; the result is unchanged."""
+    from paper_2312_12285_amd import synth
+    t, p = synth.uniform_sphere(20_000, 31)
+    w = synth.lognormal_weights(20_000, 0.3, 32)
+    a = cplx(lib.alm_from_points_spline(dev(t), dev(p), dev(w), 48, 120, 0.05))
+    b = cplx(lib.alm_from_points_spline(dev(t), dev(p), dev(w), 48, 120, 0.05, options=lib.opts(timing=1)))
+    ms = lib.last_timing_ms()
+    print(f"binning kernel {ms:.3f} ms", flush=True)
+    assert ms > 0.0
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
