@@ -64,6 +64,31 @@ __global__ void count_kernel(const double *__restrict__ theta, int64_t n, double
         atomicAdd(&counts[interval_of(theta[i], theta_cut, h, n_int)], 1u);
 }
 
+// The same counts through a per-workgroup histogram in LDS (nb <= kHistMax
+// buckets): workgroup b takes the contiguous chunk [b chunk, (b+1) chunk) of the
+// points, counts it with LDS atomics and adds each nonzero bucket to the global
+// count once, so contention on the global counters drops by the chunk's
+// points per bucket.
+constexpr int kHistMax = 16384;      // buckets held in LDS (64 KB)
+constexpr int kHistThreads = 1024;
+constexpr int kHistBlocks = 512;
+
+__global__ __launch_bounds__(kHistThreads) void count_lds_kernel(const double *__restrict__ theta, int64_t n,
+                                                                double theta_cut, double h, int n_int, int64_t chunk,
+                                                                unsigned *__restrict__ counts) {
+    extern __shared__ unsigned hist[];
+    const int nb = n_int + 1;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+        atomicAdd(&hist[interval_of(theta[i], theta_cut, h, n_int)], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+}
+
 // offsets[b] = sum_{b' < b} counts[b'] for b <= nb (nb buckets), one workgroup;
 // cursors reset to 0
 __global__ __launch_bounds__(1024) void scan_kernel(const unsigned *__restrict__ counts, int nb,
@@ -108,6 +133,50 @@ __global__ void scatter_kernel(const double *__restrict__ theta, const double *_
         const double th = theta[i], ph = phi[i], wi = w[i];
         const int j = interval_of(th, theta_cut, h, n_int);
         const int64_t pos = offsets[j] + atomicAdd(&cursors[j], 1u);
+        if (j == n_int) {
+            const int64_t p = pos - offsets[n_int];
+            pth[p] = th;
+            pph[p] = ph;
+            pw[p] = wi;
+            continue;
+        }
+        const double x = cos(th);
+        const double t = (x - xn[j]) / (xn[j + 1] - xn[j]);
+        const double u = 1.0 - t;
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        double2 *dst = (double2 *)(q + pos * kPointDoubles);
+        dst[0] = make_double2(wi * ((2.0 * t + 1.0) * u * u), wi * (t * u * u));
+        dst[1] = make_double2(wi * (t * t * (3.0 - 2.0 * t)), wi * (t * t * (t - 1.0)));
+        dst[2] = make_double2(ph * kInv2Pi, cp);
+        dst[3] = make_double2(sp, 0.0);
+    }
+}
+
+// The scatter with the same chunks: each workgroup counts its chunk per bucket
+// in LDS, reserves that many places per bucket with one global atomic, then
+// hands out places inside its reservation with LDS atomics.
+__global__ __launch_bounds__(kHistThreads) void scatter_lds_kernel(
+    const double *__restrict__ theta, const double *__restrict__ phi, const double *__restrict__ w, int64_t n,
+    double theta_cut, double h, int n_int, int64_t chunk, const double *__restrict__ xn,
+    const int64_t *__restrict__ offsets, unsigned *__restrict__ cursors, double *__restrict__ q,
+    double *__restrict__ pth, double *__restrict__ pph, double *__restrict__ pw) {
+    extern __shared__ unsigned hist[];
+    const int nb = n_int + 1;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+        atomicAdd(&hist[interval_of(theta[i], theta_cut, h, n_int)], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+        if (hist[b]) hist[b] = atomicAdd(&cursors[b], hist[b]);   // first place of this workgroup's run
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double th = theta[i], ph = phi[i], wi = w[i];
+        const int j = interval_of(th, theta_cut, h, n_int);
+        const int64_t pos = offsets[j] + atomicAdd(&hist[j], 1u);
         if (j == n_int) {
             const int64_t p = pos - offsets[n_int];
             pth[p] = th;
@@ -593,8 +662,14 @@ hipError_t launch_spline_count(const double *theta, int64_t n, double theta_cut,
     hipLaunchKernelGGL(nodes_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, stream, theta_cut, h, n_nodes, xn, thn);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n > 0) {
-        hipLaunchKernelGGL(count_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, n, theta_cut, h,
-                           n_nodes - 1, counts);
+        if (n_nodes <= kHistMax) {
+            const int64_t chunk = (n + kHistBlocks - 1) / kHistBlocks;
+            hipLaunchKernelGGL(count_lds_kernel, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kHistThreads),
+                               sizeof(unsigned) * n_nodes, stream, theta, n, theta_cut, h, n_nodes - 1, chunk, counts);
+        } else {
+            hipLaunchKernelGGL(count_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, n, theta_cut,
+                               h, n_nodes - 1, counts);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -608,8 +683,15 @@ hipError_t launch_spline_scatter(const double *theta, const double *phi, const d
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, counts, nb, offsets, cursors);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n == 0) return e;
-    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, phi, w, n, theta_cut,
-                       h, n_nodes - 1, xn, (const int64_t *)offsets, cursors, q, n_spline, pth, pph, pw);
+    if (n_nodes <= kHistMax) {
+        const int64_t chunk = (n + kHistBlocks - 1) / kHistBlocks;
+        hipLaunchKernelGGL(scatter_lds_kernel, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kHistThreads),
+                           sizeof(unsigned) * n_nodes, stream, theta, phi, w, n, theta_cut, h, n_nodes - 1, chunk, xn,
+                           (const int64_t *)offsets, cursors, q, pth, pph, pw);
+    } else {
+        hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, phi, w, n, theta_cut,
+                           h, n_nodes - 1, xn, (const int64_t *)offsets, cursors, q, n_spline, pth, pph, pw);
+    }
     return hipGetLastError();
 }
 

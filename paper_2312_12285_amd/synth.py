@@ -1,7 +1,7 @@
 """Seeded synthetic point catalogs (numpy PCG64), shared by tests, bench and smoke.
 
 Nothing here evaluates the transform: this module only draws positions and
-weights.  Workload recipes (stated in the design doc):
+weights.  Workload recipes:
 
 * full sky: cos(theta) ~ U[-1, 1], phi ~ U[0, 2pi), unit weights;
 * survey mask: positions read as equatorial (dec = 90deg - theta, RA = phi),

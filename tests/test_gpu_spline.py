@@ -1,7 +1,9 @@
 """GPU interpolated transform (App. A.2) against the oracle's interpolated transform.
 
-Both evaluate the same approximation (same nodes, same Hermite basis, same
-polar split), so they agree to rounding: gate 1e-10 per-l norm-wise relative
+The node counts cover both ways of sorting the points into intervals
+(per-workgroup LDS histograms up to 16384 nodes, global atomics above).  Both
+evaluate the same approximation (same nodes, same Hermite basis, same polar
+split), so they agree to rounding: gate 1e-10 per-l norm-wise relative
 (the direct path's gate), element-wise 1e-10 of the l-row norm.  Also: the
 spline path converges to the exact GPU direct sum like h^4, a cut that makes
 every point polar reduces it to the direct sum, empty input, argument checks.
@@ -43,7 +45,8 @@ def per_l(got, ref, lmax):
 
 
 @pytest.mark.parametrize("n,lmax,n_nodes,cut_deg,seed", [(20_000, 64, 200, 5.0, 1), (7_001, 100, 37, 20.0, 2),
-                                                          (30_000, 40, 513, 0.5, 3), (5_000, 3, 2, 30.0, 4)])
+                                                          (30_000, 40, 513, 0.5, 3), (5_000, 3, 2, 30.0, 4),
+                                                          (40_000, 12, 20_000, 2.0, 5)])
 def test_spline_matches_oracle(lib, oracle, n, lmax, n_nodes, cut_deg, seed):
     from oracle import spline
     from paper_2312_12285_amd import synth
