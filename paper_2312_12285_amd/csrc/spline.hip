@@ -197,6 +197,16 @@ __global__ __launch_bounds__(kHistThreads) void scatter_lds_kernel(
     }
 }
 
+constexpr int kPhaseN = 1024;    // entries of the phase table e^{2 pi i k / kPhaseN}
+
+__global__ void phase_table_kernel(double2 *__restrict__ tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kPhaseN) return;
+    double s, c;
+    sincospi(2.0 * k / kPhaseN, &s, &c);
+    tab[k] = make_double2(c, s);
+}
+
 constexpr int kBinM = 8;         // orders per binning wave
 constexpr int kBinThreads = 64;  // one wave per (interval, kBinM orders)
 constexpr int kBinVals = kBinM * 8;   // sums per wave: 4 basis functions x (re, im) per order
@@ -212,7 +222,8 @@ constexpr int kBinPts = 2;       // points per lane per iteration
 // sums the current ones); the 64 sums per lane are then added across the wave.
 __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__restrict__ q, int64_t n_spline,
                                                           const int64_t *__restrict__ offsets, int n_int, int lmax,
-                                                          int n_pass, double2 *__restrict__ v) {
+                                                          int n_pass, const double2 *__restrict__ ptab,
+                                                          double2 *__restrict__ v) {
     const int64_t k = blockIdx.x >> 3;   // position in this XCD's sequence
     const int64_t jj = (int64_t)(blockIdx.x & 7) + 8 * (k / n_pass);
     const int pass = (int)(k % n_pass);
@@ -250,6 +261,10 @@ __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__res
             for (int a = 0; a < 4; ++a) nx[b][a] = rec[rr * 4 + a];
         }
     };
+    // e^{2 pi i k / kPhaseN} in LDS for the phase of every point below
+    __shared__ double2 stab[kPhaseN];
+    for (int k = lane; k < kPhaseN; k += kBinThreads) stab[k] = ptab[k];
+    wave_lds_sync();
     // Per point and pass: e^{-i m0 phi} and e^{-i (m0-1) phi}, then the orders
     // m0 .. m0+7 by the two-term recurrence z_{m+1} = 2 cos(phi) z_m - z_{m-1}
     // (two FMAs per order).  Iterations whose points all lie in the interval
@@ -268,8 +283,20 @@ __global__ __launch_bounds__(kBinThreads, 2) void bin_kernel(const double *__res
             const double p = (double)m0 * tph;
             const double pe = fma((double)m0, tph, -p);
             const double fr = (p - floor(p)) + pe;      // m0 phi / (2 pi) mod 1, within 2^-52
-            double sm, cm;
-            sincospi(2.0 * fr, &sm, &cm);
+            // e^{2 pi i fr} = table[k] e^{i eps}: k = floor(kPhaseN fr) (clamped: fr may leave
+            // [0, 1) by an ulp), eps = 2 pi (fr - k / kPhaseN) formed from an exact difference,
+            // |eps| <= 2 pi / kPhaseN, and cos/sin of eps by their Taylor series to eps^6 / eps^5
+            // (the next terms are below 1e-19)
+            const double f = fr * (double)kPhaseN;
+            int k = (int)floor(f);
+            k = k < 0 ? 0 : (k > kPhaseN - 1 ? kPhaseN - 1 : k);
+            const double eps = (f - (double)k) * (6.283185307179586476925 / kPhaseN);
+            const double e2 = eps * eps;
+            const double ce = fma(e2, fma(e2, fma(e2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+            const double se = eps * fma(e2, fma(e2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
+            const double2 tk = stab[k];
+            const double cm = fma(tk.x, ce, -tk.y * se);
+            const double sm = fma(tk.x, se, tk.y * ce);
             zr[b] = cm;           // e^{-i m0 phi}
             zi[b] = -sm;
             // e^{-i (m0 - 1) phi} = (cm - i sm)(c1 + i s1)
@@ -648,7 +675,7 @@ SplinePlan spline_plan(int64_t n, int lmax, int n_nodes) {
     p.ns_ranges = want < lmax + 1 ? (want > 0 ? want : 1) : lmax + 1;
     // node-sum partials (4 per (l, m) and slice), alpha table, scale table
     p.state_doubles = (size_t)p.ns_slices * 4 * (size_t)tri_size(lmax) + (size_t)coef_table_size(lmax) +
-                      (size_t)tri_size(lmax);
+                      (size_t)tri_size(lmax) + 2 * (size_t)kPhaseN;   // + the phase table
     (void)n;
     return p;
 }
@@ -702,11 +729,14 @@ hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t
     double *partial = state;
     double *coef = partial + (size_t)p.ns_slices * 4 * (size_t)tri_size(lmax);
     double *sig = coef + coef_table_size(lmax);
+    double *ptab = sig + tri_size(lmax);
+    hipLaunchKernelGGL(phase_table_kernel, dim3(kPhaseN / 256), dim3(256), 0, stream, (double2 *)ptab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int64_t per_xcd = (int64_t)((p.n_int + 7) / 8) * p.n_pass;   // units per XCD
-    hipError_t e;
     if (bin_start && (e = hipEventRecord(bin_start, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)(per_xcd * 8)), dim3(kBinThreads), 0, stream, q, n_spline, offsets,
-                       p.n_int, lmax, p.n_pass, v);
+                       p.n_int, lmax, p.n_pass, (const double2 *)ptab, v);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (bin_stop && (e = hipEventRecord(bin_stop, stream)) != hipSuccess) return e;
     const int64_t total = (int64_t)(lmax + 1) * n_nodes;
