@@ -147,3 +147,14 @@ def test_empty_tiny_and_arguments(lib):
         lib.shear_alm_from_points(*a, 16384)
     with pytest.raises(ValueError):
         lib.shear_alm_from_points(a[0], a[1], a[2], a[3], dev(g2[:50]), 10)
+
+
+def test_phase_periodicity(lib):
+    """phi and phi + 2 pi k (negative angles included) give the same E and B."""
+    t, p, w, g1, g2 = catalog(8_000, 51)
+    k = np.random.default_rng(52).integers(-3, 6, size=p.size)
+    a = [cplx(x) for x in lib.shear_alm_from_points(dev(t), dev(p), dev(w), dev(g1), dev(g2), 120)]
+    b = [cplx(x) for x in lib.shear_alm_from_points(dev(t), dev(p + 2 * math.pi * k), dev(w), dev(g1), dev(g2), 120)]
+    for x, y in zip(a, b):
+        err, norm, L = per_l(y, x, 120)
+        assert err[2:].max() <= 1e-12

@@ -110,3 +110,17 @@ def test_timing_option_times_the_binning_kernel(lib):
     print(f"binning kernel {ms:.3f} ms", flush=True)
     assert ms > 0.0
     assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_phase_periodicity(lib):
+    """phi and phi + 2 pi k (k = -3 .. 5, negative angles included) give the same a_lm: the
+    binning reduces m0 phi / (2 pi) modulo 1 itself."""
+    from paper_2312_12285_amd import synth
+    t, p = synth.uniform_sphere(30_000, 41)
+    w = synth.lognormal_weights(30_000, 0.3, 42)
+    k = np.random.default_rng(43).integers(-3, 6, size=p.size)
+    a = cplx(lib.alm_from_points_spline(dev(t), dev(p), dev(w), 200, 400, 0.05))
+    b = cplx(lib.alm_from_points_spline(dev(t), dev(p + 2 * math.pi * k), dev(w), 200, 400, 0.05))
+    err, norm = per_l(b, a, 200)
+    print(f"phase periodicity: per-l max rel diff {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-12
