@@ -128,3 +128,22 @@ def test_extended_call_rejects_bad_workspace_and_sizes(lib):
     assert f(fake, fake, fake, 10 ** 9, 16383, fake, ctypes.byref(big), None, 0, None) == -1
     big = _Opts(3, 16, 0, 0, 512, 0, 0, 0)                                                  # 512 x 16384 items
     assert f(fake, fake, fake, 10 ** 9, 16383, fake, ctypes.byref(big), None, 0, None) == -1
+
+
+def test_shear_workspace_bytes(lib):
+    """Scratch of the spin transform: S slices x 4T doubles (both spins, re and im), with S the
+    point groups of 64 x points-per-lane, at most 32 by default; 0 for what the call rejects."""
+    f = lib.ptalm_shear_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_Opts)]
+    T = lambda lmax: (lmax + 1) * (lmax + 2) // 2
+    for n, lmax, kp, S in [(10 ** 7, 3072, 0, 0), (1000, 64, 0, 0), (1000, 64, 2, 0), (100_000, 200, 4, 5)]:
+        groups = (n + 64 * (kp or 4) - 1) // (64 * (kp or 4))
+        s = min(S if S else 32, max(1, groups))
+        o = _Opts(0, 0, kp, 8 if kp else 0, S, 0, 0, 0)
+        assert f(n, lmax, ctypes.byref(o)) == 8 * 4 * T(lmax) * s
+    assert f(1000, 64, None) == 8 * 4 * T(64) * 4                                   # NULL options
+    assert f(1000, 64, ctypes.byref(_Opts(1, 0, 0, 0, 0, 0, 0, 0))) == 0          # FP64 only
+    assert f(1000, 64, ctypes.byref(_Opts(0, 2, 0, 0, 0, 0, 0, 0))) == 0          # one weight vector
+    assert f(1000, 64, ctypes.byref(_Opts(0, 0, 9, 8, 0, 0, 0, 0))) == 0          # no such variant
+    assert f(-1, 64, None) == 0 and f(10, 16384, None) == 0
