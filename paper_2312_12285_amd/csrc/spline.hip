@@ -403,7 +403,7 @@ __global__ void node_weights_kernel(const double2 *__restrict__ v, const double 
     }
 }
 
-constexpr int kNsKP = 4;            // node sum: nodes per lane
+constexpr int kNsKP = 5;            // node sum: nodes per lane
 constexpr int kNsLB = 8;            // node sum: degrees per register block
 constexpr int kNsMaxSlices = 8;     // node sum: node slices (partial columns)
 constexpr int kNsItems = 16384;     // node sum: target (slice, order range) items
