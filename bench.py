@@ -86,38 +86,45 @@ WORKLOADS = {
 
 
 PROFILES = os.path.join(HERE, "profiles")
-# the kernel and the work plan that decides its launch (a change to either voids recorded traffic)
+# the kernel and the work plan that decides its launch, per workload with a recorded traffic
+# summary (a change to either voids the record)
 CSRC = os.path.join(HERE, "paper_2312_12285_amd", "csrc")
-KERNEL_SOURCES = [os.path.join(CSRC, f) for f in ("alm_direct.hip", "wave_common.h")]
-PLAN_SOURCE = (os.path.join(CSRC, "api.hip"), "// Default kernel variant and decomposition.", "size_t align256(size_t b)")
+TRAFFIC_SOURCES = {
+    "randoms3072": (["alm_direct.hip", "wave_common.h"],
+                    ("api.hip", "// Default kernel variant and decomposition.", "size_t align256(size_t b)")),
+    "spline3072": (["spline.hip", "wave_common.h"], None),
+}
 
 
-def kernel_source_hash():
-    """sha256 (first 16 hex digits) of the transform kernel's sources and of the part of
-    api.hip that picks its launch (defaults, slices, m-ranges)."""
+def kernel_source_hash(workload="randoms3072"):
+    """sha256 (first 16 hex digits) of the dominant kernel's sources and of the part of
+    api.hip that picks its launch, for a workload with a recorded traffic summary."""
     import hashlib
+    files, plan = TRAFFIC_SOURCES[workload]
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
+    for name in files:
+        with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
-    path, start, end = PLAN_SOURCE
-    with open(path) as f:
-        text = f.read()
-    h.update(text[text.index(start):text.index(end)].encode())
+    if plan is not None:
+        name, start, end = plan
+        with open(os.path.join(CSRC, name)) as f:
+            text = f.read()
+        h.update(text[text.index(start):text.index(end)].encode())
     return h.hexdigest()[:16]
 
 
 def recorded_traffic(workload, variant):
-    """HBM bytes per launch of the transform kernel from the committed rocprofv3
-    PMC summary (FETCH_SIZE, WRITE_SIZE scaled by a copy-kernel calibration), or
-    None when no summary exists for this workload/variant or the kernel source
-    changed since the counters were taken."""
+    """HBM bytes per launch of the workload's dominant kernel from the committed rocprofv3
+    PMC summary (FETCH_SIZE, WRITE_SIZE scaled by a copy-kernel calibration), or None when
+    no summary exists for this workload/variant or its sources changed since."""
+    if workload not in TRAFFIC_SOURCES:
+        return None
     path = os.path.join(PROFILES, f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash() or rec.get("variant") != variant:
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash(workload) or rec.get("variant") != variant:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -346,7 +353,8 @@ def run_spline(args, cats, lmax):
     flops = SPLINE_FLOPS_PER_TERM * (n - n_polar) * (lmax + 1)
     achieved = flops / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(args.workload if args.scale == 1.0 else None, "bin_kernel"),
                 "kernel": "bin_kernel (per-m binned Hermite weights)", "kernel_ms_per_launch": round(k_ms, 3),
                 "flops_per_point_m": SPLINE_FLOPS_PER_TERM, "call_ms": round(call_ms, 3),
                 "call_tflops": round(flops / (call_ms * 1e-3) / 1e12, 3)}
