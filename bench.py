@@ -393,7 +393,7 @@ def run_spline(args, cats, lmax):
               flush=True)
         pairs = [(lmax, 0), (lmax, lmax // 2), (2 * lmax // 3, 100), (lmax // 3, lmax // 3 - 1), (lmax // 6, 7),
                  (lmax, lmax), (10, 5), (lmax // 2, 1)]
-        k = min(n, int(3e6 * 3073 / (lmax + 1)))
+        k = min(n, int(7e6 * 3073 / (lmax + 1)))
         t1 = time.time()
         spline.alm_spline_entries(cat.theta[:k], cat.phi[:k], cat.w[:k], lmax, nodes, cut, pairs)
         dt = time.time() - t1
