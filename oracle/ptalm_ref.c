@@ -16,7 +16,7 @@
  *     Pbar_l^m = sqrt((l-m)/(l+m)) [ (2l-1)/(l-m) x Pbar_{l-1}^m
  *                 - sqrt((l-m-1)/(l+m-1)) (l+m-1)/(l-m) Pbar_{l-2}^m ].
  *
- * Readings where the paper is silent (each listed in the design doc):
+ * Readings where the paper is silent:
  *  - sqrt(1-x^2) is taken as sin(theta) computed from theta: the printed form
  *    loses all relative accuracy near the poles.
  *  - The sectoral recurrence, unrolled, is Pbar_m^m = (-1)^m c_m s^m with

@@ -150,7 +150,7 @@ def golden_spiral(n: int, perturb: float = 0.0, seed: int = 0):
 
 
 # ----------------------------------------------------------------------------------------
-# The five workloads (sizes as published for this build's configurations)
+# The five benchmark workloads and their sizes
 # ----------------------------------------------------------------------------------------
 
 @dataclasses.dataclass
