@@ -1,0 +1,133 @@
+"""Parity at the largest degree the library accepts, lmax = 16383 (T = 1.34e8 coefficients,
+the limit that keeps every coefficient index in 32 bits).
+
+A small full-sky catalog keeps the GPU work light while every table, scratch
+buffer and index runs to its maximum extent:
+
+* FP64: sampled coefficients against the oracle over every point (<= 1e-10 of
+  the rms at their l), including the last column m = 16383;
+* single points at the poles: the closed form a_l0 = w sqrt((2l+1)/4pi), times
+  (-1)^l at the south pole, over the whole m = 0 column; exact zeros at m > 0
+  at the north pole (sin theta = 0), and the oracle's values at the south pole,
+  where sin(theta) of the rounded pi is 1.2e-16;
+* the mixed form against FP64 (global <= 1e-6);
+* the spin +-2 transform: sampled E and B coefficients against the spin oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+LMAX = 16383
+GATE = 1e-10
+EPS = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2312_12285_amd import ptalm
+    return ptalm
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(*arrs):
+    import torch
+    return [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+PAIRS = [(2, 0), (2, 1), (2, 2), (5000, 17), (8191, 8191), (12000, 6000), (16383, 0), (16383, 1),
+         (16383, 8191), (16383, 16382), (16383, 16383)]
+
+
+def sampled(lib, alm_dev, pairs):
+    """The coefficients at pairs, gathered on the device."""
+    import torch
+    idx = torch.tensor([lib.alm_index(LMAX, l, m) for l, m in pairs], device=alm_dev.device)
+    return lib.as_complex(alm_dev)[idx].cpu().numpy()
+
+
+def catalog():
+    from paper_2312_12285_amd.synth import uniform_sphere
+    t, p = uniform_sphere(190, 71)
+    w = np.random.default_rng(72).uniform(0.5, 1.5, t.size)
+    return t, p, w
+
+
+def test_fp64_and_mixed_at_maximum_lmax(lib, oracle):
+    import torch
+    say(f"case: 190 full-sky points, lmax {LMAX}, FP64")
+    t, p, w = catalog()
+    d = dev(t, p, w)
+    a = lib.alm_from_points(*d, LMAX)
+    torch.cuda.synchronize()
+    ls = np.array([l for l, _ in PAIRS]); ms = np.array([m for _, m in PAIRS])
+    want = oracle.alm_entries(t, p, w, ls, ms)
+    cl = lib.cl_from_alm(a, LMAX).cpu().numpy()
+    rel = np.abs(sampled(lib, a, PAIRS) - want) / np.sqrt(cl[ls])
+    say(f"fp64: sampled entries, max |err| / rms_l = {rel.max():.3e}")
+    assert rel.max() <= GATE
+    assert abs(a[0].item() - math.fsum(w) / math.sqrt(4 * math.pi)) <= 1e-13 * a[0].item()
+
+    say(f"case: 190 full-sky points, lmax {LMAX}, mixed")
+    b = lib.alm_from_points(*d, LMAX, options=lib.opts(precision=lib.MIXED))
+    torch.cuda.synchronize()
+    g = (torch.linalg.norm(b - a) / torch.linalg.norm(a)).item()
+    say(f"mixed vs fp64: global {g:.3e}")
+    assert g <= 1e-6
+
+
+@pytest.mark.parametrize("theta,sign", [(0.0, 1.0), (math.pi, -1.0)])
+def test_poles_at_maximum_lmax(lib, oracle, theta, sign):
+    import torch
+    say(f"case: single point theta={theta}, lmax {LMAX}")
+    wv = 1.7
+    d = dev(np.array([theta]), np.array([0.3]), np.array([wv]))
+    a = lib.alm_from_points(*d, LMAX)
+    torch.cuda.synchronize()
+    col0 = lib.as_complex(a[: 2 * (LMAX + 1)]).cpu().numpy()     # m = 0, l = 0..lmax
+    l = np.arange(LMAX + 1)
+    want = wv * np.sqrt((2 * l + 1) / (4 * math.pi)) * sign ** l
+    rel = np.abs(col0 - want) / np.abs(want)
+    # rounding of the recurrence grows linearly in l at x = +-1 (the oracle's own FP64 sum: 2.1e-11)
+    say(f"pole m = 0 column: max rel err {rel.max():.3e} (bound {64 * LMAX * EPS:.1e})")
+    assert rel.max() <= 64 * LMAX * EPS
+    rest = lib.as_complex(a[2 * (LMAX + 1):])
+    if theta == 0.0:
+        assert torch.count_nonzero(rest).item() == 0        # sin(theta) = 0: every m > 0 vanishes
+    else:
+        pairs = [(LMAX, 1), (LMAX, 2), (5000, 1), (LMAX, 100), (LMAX, LMAX)]
+        want = oracle.alm_entries(np.array([theta]), np.array([0.3]), np.array([wv]),
+                                  [q[0] for q in pairs], [q[1] for q in pairs])
+        got = sampled(lib, a, pairs)
+        rms = wv / math.sqrt(4 * math.pi)      # rms at every l: only m = 0 is of order one
+        say(f"south pole m > 0: got {np.abs(got)}, oracle {np.abs(want)}")
+        assert np.all(np.abs(got - want) <= GATE * rms)
+        assert torch.abs(rest).max().item() <= 1e-6       # m >= 1 carries sin(theta)^m = (1.2e-16)^m
+
+
+def test_spin_at_maximum_lmax(lib, oracle):
+    import torch
+    from paper_2312_12285_amd.synth import shear_components
+    say(f"case: shear, 190 full-sky points, lmax {LMAX}")
+    t, p, w = catalog()
+    g1, g2 = shear_components(t.size, seed=73)
+    e, b = lib.shear_alm_from_points(*dev(t, p, w, g1, g2), LMAX)
+    torch.cuda.synchronize()
+    ls = [l for l, _ in PAIRS]
+    ms = [m for _, m in PAIRS]
+    we, wb = oracle.shear_eb_entries(t, p, w, g1, g2, ls, ms)
+    for name, got, want in (("E", e, we), ("B", b, wb)):
+        cl = lib.cl_from_alm(got, LMAX).cpu().numpy()
+        rel = np.abs(sampled(lib, got, PAIRS) - want) / np.sqrt(cl[ls])
+        say(f"shear {name}: sampled entries, max |err| / rms_l = {rel.max():.3e}")
+        assert rel.max() <= GATE
