@@ -11,7 +11,8 @@ buffer and index runs to its maximum extent:
   at the north pole (sin theta = 0), and the oracle's values at the south pole,
   where sin(theta) of the rounded pi is 1.2e-16;
 * the mixed form against FP64 (global <= 1e-6);
-* the spin +-2 transform: sampled E and B coefficients against the spin oracle.
+* the spin +-2 transform: sampled E and B coefficients against the spin oracle;
+* the interpolated transform: sampled coefficients against the oracle's.
 """
 import math
 import sys
@@ -131,3 +132,24 @@ def test_spin_at_maximum_lmax(lib, oracle):
         rel = np.abs(sampled(lib, got, PAIRS) - want) / np.sqrt(cl[ls])
         say(f"shear {name}: sampled entries, max |err| / rms_l = {rel.max():.3e}")
         assert rel.max() <= GATE
+
+
+def test_interpolated_transform_at_maximum_lmax(lib):
+    """App. A.2 at lmax 16383 (2000 nodes, 1-degree caps; two points inside the caps take the
+    exact sum): sampled coefficients against the oracle's interpolated transform."""
+    import torch
+    from oracle import spline
+    say(f"case: interpolated transform, 192 points, lmax {LMAX}, 2000 nodes")
+    t, p, w = catalog()
+    t = np.concatenate([t, [0.01, math.pi - 0.005]])
+    p = np.concatenate([p, [1.1, 4.0]])
+    w = np.concatenate([w, [0.9, 1.2]])
+    nodes, cut = 2000, math.radians(1.0)
+    a = lib.alm_from_points_spline(*dev(t, p, w), LMAX, nodes, cut)
+    torch.cuda.synchronize()
+    pairs = [(2, 0), (5000, 17), (8191, 8191), (16383, 0), (16383, 8191), (16383, 16383)]
+    want = spline.alm_spline_entries(t, p, w, LMAX, nodes, cut, pairs)
+    cl = lib.cl_from_alm(a, LMAX).cpu().numpy()
+    rel = np.abs(sampled(lib, a, pairs) - want) / np.sqrt(cl[[l for l, _ in pairs]])
+    say(f"spline: sampled entries, max |err| / rms_l = {rel.max():.3e}")
+    assert rel.max() <= GATE
