@@ -198,6 +198,9 @@ int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, in
  * ------------------------------------------------------------------------ */
 
 #define PTALM_SPLINE_NODES_MAX 65536
+/* Largest point count of the interpolated transform: points are counted per interval
+ * in 32-bit counters. */
+#define PTALM_SPLINE_N_MAX 4294967295LL
 
 /* a_lm ~= sum_i w_i Y*_lm(theta_i, phi_i) by the interpolated transform of
  * App. A.2, same arguments and output layout as ptalm_alm_from_points:
@@ -218,7 +221,7 @@ int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, in
  * calls can differ in the last bits.  opts: NULL, or opts->timing != 0 to
  * record HIP events around the binning kernel (the dominant one) on `stream`,
  * read with ptalm_last_timing(); the other fields are not used.
- * PTALM_EINVAL on bad sizes or pointers. */
+ * PTALM_EINVAL on bad sizes or pointers, or n > PTALM_SPLINE_N_MAX. */
 int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
                                  int n_nodes, double theta_cut, double *alm, const ptalm_opts *opts,
                                  void *stream);

@@ -517,6 +517,7 @@ int ptalm_alm_from_points_spline(const double *theta, const double *phi, const d
                                  int n_nodes, double theta_cut, double *alm, const ptalm_opts *opts, void *stream_) {
     g_error.clear();
     if (n < 0) return fail(PTALM_EINVAL, "n < 0");
+    if (n > PTALM_SPLINE_N_MAX) return fail(PTALM_EINVAL, "n above PTALM_SPLINE_N_MAX (32-bit per-interval counters)");
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
     if (alm == nullptr || (n > 0 && (theta == nullptr || phi == nullptr || w == nullptr)))
         return fail(PTALM_EINVAL, "NULL pointer");

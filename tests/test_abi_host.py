@@ -147,3 +147,19 @@ def test_shear_workspace_bytes(lib):
     assert f(1000, 64, ctypes.byref(_Opts(0, 2, 0, 0, 0, 0, 0, 0))) == 0          # one weight vector
     assert f(1000, 64, ctypes.byref(_Opts(0, 0, 9, 8, 0, 0, 0, 0))) == 0          # no such variant
     assert f(-1, 64, None) == 0 and f(10, 16384, None) == 0
+
+
+def test_spline_rejects_point_counts_above_its_counters(lib):
+    """The interpolated transform counts points per interval in 32 bits: n above 2^32 - 1 is
+    refused before any device call (fake device pointers)."""
+    f = lib.ptalm_alm_from_points_spline
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.ptalm_last_error.restype = ctypes.c_char_p
+    fake = 1 << 40
+    assert f(fake, fake, fake, 2 ** 32, 64, 100, 0.01, fake, None, None) == -1
+    assert b"PTALM_SPLINE_N_MAX" in lib.ptalm_last_error()
+    assert f(fake, fake, fake, -1, 64, 100, 0.01, fake, None, None) == -1
+    assert f(fake, fake, fake, 10, 64, 1, 0.01, fake, None, None) == -1           # n_nodes < 2
+    assert f(fake, fake, fake, 10, 64, 100, 2.0, fake, None, None) == -1          # theta_cut >= pi/2
