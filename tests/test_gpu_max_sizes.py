@@ -1,8 +1,8 @@
-"""Parity at the largest degree the library accepts, lmax = 16383 (T = 1.34e8 coefficients,
-the limit that keeps every coefficient index in 32 bits).
+"""Parity at the largest sizes the library accepts.
 
-A small full-sky catalog keeps the GPU work light while every table, scratch
-buffer and index runs to its maximum extent:
+lmax = 16383 (T = 1.34e8 coefficients, the limit that keeps every coefficient
+index in 32 bits). A small full-sky catalog keeps the GPU work light while every
+table, scratch buffer and index runs to its maximum extent:
 
 * FP64: sampled coefficients against the oracle over every point (<= 1e-10 of
   the rms at their l), including the last column m = 16383;
@@ -13,6 +13,12 @@ buffer and index runs to its maximum extent:
 * the mixed form against FP64 (global <= 1e-6);
 * the spin +-2 transform: sampled E and B coefficients against the spin oracle;
 * the interpolated transform: sampled coefficients against the oracle's.
+
+n = 2^31 + 777 points (point indices past the 32-bit range, 51.5 GB of inputs):
+a base catalog of 2^20 points repeated 2048 times, then its first 777 points.
+The transform is linear in the catalog, so a_lm = 2048 a_lm(base) + a_lm(first
+777) in exact arithmetic, both terms from the oracle; checked for the FP64 path
+and the spin transform at lmax 64 over every coefficient.
 """
 import math
 import sys
@@ -153,3 +159,41 @@ def test_interpolated_transform_at_maximum_lmax(lib):
     rel = np.abs(sampled(lib, a, pairs) - want) / np.sqrt(cl[[l for l, _ in pairs]])
     say(f"spline: sampled entries, max |err| / rms_l = {rel.max():.3e}")
     assert rel.max() <= GATE
+
+
+def test_point_count_above_2_to_31(lib, oracle):
+    import torch
+    from conftest import per_l_rel_err
+    from paper_2312_12285_amd.synth import masked_galaxies, shear_components
+    lmax, B, K, r = 64, 2 ** 20, 2048, 777
+    n = K * B + r
+    say(f"case: n = {n} (2^31 + {r}): 2^20 masked galaxies x {K} + {r}, lmax {lmax}")
+    g = masked_galaxies(B, seed_pos=81, seed_w=82)
+    g1, g2 = shear_components(B, seed=83)
+    base = dev(g.theta, g.phi, g.w, g1, g2)
+    big = []
+    for x in base:
+        y = torch.empty(n, dtype=torch.float64, device=x.device)
+        y[: K * B].view(K, B).copy_(x.expand(K, B))
+        y[K * B:].copy_(x[:r])
+        big.append(y)
+    del base
+
+    a = lib.alm_from_points(*big[:3], lmax)
+    torch.cuda.synchronize()
+    want = K * oracle.alm_from_points(g.theta, g.phi, g.w, lmax) + \
+        oracle.alm_from_points(g.theta[:r], g.phi[:r], g.w[:r], lmax)
+    err = per_l_rel_err(lib.as_complex(a).cpu().numpy(), want, lmax)
+    say(f"fp64: max per-l err {err.max():.3e}")
+    assert err.max() <= GATE
+
+    e, b = lib.shear_alm_from_points(*big, lmax)
+    torch.cuda.synchronize()
+    del big
+    torch.cuda.empty_cache()
+    we, wb = oracle.shear_eb(g.theta, g.phi, g.w, g1, g2, lmax)
+    fe, fb = oracle.shear_eb(g.theta[:r], g.phi[:r], g.w[:r], g1[:r], g2[:r], lmax)
+    for name, got, want in (("E", e, K * we + fe), ("B", b, K * wb + fb)):
+        err = per_l_rel_err(lib.as_complex(got).cpu().numpy(), want, lmax)[2:]   # l < 2 is zero
+        say(f"shear {name}: max per-l err {err.max():.3e}")
+        assert err.max() <= GATE
