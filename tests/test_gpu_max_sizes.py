@@ -12,7 +12,9 @@ table, scratch buffer and index runs to its maximum extent:
   where sin(theta) of the rounded pi is 1.2e-16;
 * the mixed form against FP64 (global <= 1e-6);
 * the spin +-2 transform: sampled E and B coefficients against the spin oracle;
-* the interpolated transform: sampled coefficients against the oracle's.
+* the interpolated transform: sampled coefficients against the oracle's;
+* the mode-coupling matrix (window to l = 1024): sampled rows against the
+  oracle, zeros outside the band, and the transpose relation.
 
 n = 2^31 + 777 points (point indices past the 32-bit range, 51.5 GB of inputs):
 a base catalog of 2^20 points repeated 2048 times, then its first 777 points.
@@ -197,3 +199,28 @@ def test_point_count_above_2_to_31(lib, oracle):
         err = per_l_rel_err(lib.as_complex(got).cpu().numpy(), want, lmax)[2:]   # l < 2 is zero
         say(f"shear {name}: max per-l err {err.max():.3e}")
         assert err.max() <= GATE
+
+
+def test_coupling_matrix_at_maximum_lmax(lib, oracle):
+    """M at lmax 16383 for a window band-limited to l = 1024 (M[l][l'] = 0 for |l - l'| > 1024,
+    which the GPU must write as zeros): sampled rows against the oracle (<= 1e-12 relative,
+    element by element), and the transpose relation (2l+1) M[l][l'] = (2l'+1) M[l'][l] over the
+    whole matrix."""
+    import torch
+    from paper_2312_12285_amd.synth import window_spectrum
+    say(f"case: coupling matrix, lmax {LMAX}, window to l = 1024")
+    W = window_spectrum(1024, seed=5)
+    M = lib.coupling_matrix(dev(W)[0], LMAX)
+    torch.cuda.synchronize()
+    rows = [0, 1, 63, 64, 1100, 8190, 8191, 16382, 16383]
+    ref = oracle.coupling_rows(W, LMAX, rows)
+    got = M[rows].cpu().numpy()
+    bad = np.abs(got - ref) > 1e-12 * np.abs(ref)
+    rel = np.abs(got - ref)[ref != 0] / np.abs(ref[ref != 0])
+    say(f"coupling: sampled rows, max rel err {rel.max():.3e}, {int(bad.sum())} entries off")
+    assert not bad.any()
+    l = torch.arange(LMAX + 1, dtype=torch.float64, device=M.device)
+    sym = (2 * l[:, None] + 1) * M
+    asym = (sym - sym.T).abs().max().item()
+    say(f"coupling: transpose relation, max |diff| {asym:.3e} of max {sym.abs().max().item():.3e}")
+    assert asym <= 1e-13 * sym.abs().max().item()
