@@ -10,7 +10,8 @@ table, scratch buffer and index runs to its maximum extent:
   (-1)^l at the south pole, over the whole m = 0 column; exact zeros at m > 0
   at the north pole (sin theta = 0), and the oracle's values at the south pole,
   where sin(theta) of the rounded pi is 1.2e-16;
-* the mixed form against FP64 (global <= 1e-6);
+* the mixed form against FP64 (global <= 1e-6), and 16 weight vectors on the
+  split-bf16 matrix-core path against the oracle and FP64 (<= 1e-4);
 * the spin +-2 transform: sampled E and B coefficients against the spin oracle;
 * the interpolated transform: sampled coefficients against the oracle's;
 * the mode-coupling matrix (window to l = 1024): sampled rows against the
@@ -224,3 +225,30 @@ def test_coupling_matrix_at_maximum_lmax(lib, oracle):
     asym = (sym - sym.T).abs().max().item()
     say(f"coupling: transpose relation, max |diff| {asym:.3e} of max {sym.abs().max().item():.3e}")
     assert asym <= 1e-13 * sym.abs().max().item()
+
+
+def test_multi_weight_at_maximum_lmax(lib, oracle):
+    """16 weight vectors on the split-bf16 matrix-core path at lmax 16383 (34 GB of output):
+    sampled coefficients of two vectors against the oracle (<= 1e-4 of the l-rms, the form's
+    stated accuracy), and vector 0 against the FP64 path over every coefficient."""
+    import torch
+    say(f"case: 190 positions x 16 weight vectors, lmax {LMAX}, split-bf16 MFMA")
+    t, p, _ = catalog()
+    W = np.random.default_rng(74).uniform(0.5, 1.5, (16, t.size))
+    td, pd, wd = dev(t, p, W)
+    out = lib.alm_from_points(td, pd, wd, LMAX, options=lib.opts(precision=lib.BF16X3, n_weights=16))
+    torch.cuda.synchronize()
+    ls = np.array([l for l, _ in PAIRS]); ms = np.array([m for _, m in PAIRS])
+    for v in (0, 15):
+        want = oracle.alm_entries(t, p, W[v], ls, ms)
+        cl = lib.cl_from_alm(out[v], LMAX).cpu().numpy()
+        rel = np.abs(sampled(lib, out[v], PAIRS) - want) / np.sqrt(cl[ls])
+        say(f"bf16x3 vector {v}: sampled entries, max |err| / rms_l = {rel.max():.3e}")
+        assert rel.max() <= 1e-4
+    a64 = lib.alm_from_points(td, pd, wd[0].contiguous(), LMAX)
+    torch.cuda.synchronize()
+    g = (torch.linalg.norm(out[0] - a64) / torch.linalg.norm(a64)).item()
+    say(f"bf16x3 vs FP64, vector 0: global {g:.3e}")
+    assert g <= 1e-4
+    del out, a64
+    torch.cuda.empty_cache()
