@@ -10,7 +10,8 @@ table, scratch buffer and index runs to its maximum extent:
   (-1)^l at the south pole, over the whole m = 0 column; exact zeros at m > 0
   at the north pole (sin theta = 0), and the oracle's values at the south pole,
   where sin(theta) of the rounded pi is 1.2e-16;
-* the mixed form against FP64 (global <= 1e-6), and 16 weight vectors on the
+* the mixed form against FP64 (global <= 1e-6), the FP32 form within
+  8 (l+1) 2^-24 at each l, and 16 weight vectors on the
   split-bf16 matrix-core path against the oracle and FP64 (<= 1e-4);
 * the spin +-2 transform: sampled E and B coefficients against the spin oracle;
 * the interpolated transform: sampled coefficients against the oracle's;
@@ -252,3 +253,24 @@ def test_multi_weight_at_maximum_lmax(lib, oracle):
     assert g <= 1e-4
     del out, a64
     torch.cuda.empty_cache()
+
+
+def test_fp32_at_maximum_lmax(lib):
+    """The FP32 recurrence at lmax 16383 against the FP64 path: x = cos(theta) and the step
+    coefficients carry 2^-24 relative rounding, which shifts the phase of P_l by ~l 2^-24, so
+    the error at degree l is bounded by a small multiple of (l+1) 2^-24 (norm over m at each l)."""
+    import torch
+    say(f"case: 190 full-sky points, lmax {LMAX}, FP32 against FP64")
+    t, p, w = catalog()
+    d = dev(t, p, w)
+    a64 = lib.alm_from_points(*d, LMAX)
+    a32 = lib.alm_from_points(*d, LMAX, options=lib.opts(precision=lib.FP32))
+    torch.cuda.synchronize()
+    num = lib.cl_from_alm(a32 - a64, LMAX).cpu().numpy()
+    den = lib.cl_from_alm(a64, LMAX).cpu().numpy()
+    err = np.sqrt(num / den)
+    l = np.arange(LMAX + 1)
+    ratio = err / ((l + 1) * 2.0 ** -24)
+    say(f"fp32: per-l err at l = 64/1024/4096/16383: {err[64]:.1e} {err[1024]:.1e} {err[4096]:.1e} "
+        f"{err[LMAX]:.1e}; max err / ((l+1) 2^-24) = {ratio.max():.2f} at l = {ratio.argmax()}")
+    assert np.all(err <= np.maximum(1e-6, 8 * (l + 1) * 2.0 ** -24))
