@@ -240,9 +240,11 @@ int ptalm_alm_from_points_spline(const double *theta, const double *phi, const d
  * alm_E, alm_B: device, 2*T doubles each, healpy order (complex interleaved),
  * written completely (0 for l < 2).  FP64 throughout.
  * opts: NULL for defaults; honours points_per_lane, l_block (a compiled
- * spin variant), n_slices, m_ranges and timing (ptalm_last_timing then reads
- * the spin kernel's device time); precision must be PTALM_FP64 and n_weights
- * 0 or 1 (else PTALM_ENOTSUP).  Allocates and frees stream-ordered scratch of
+ * spin variant), n_slices, m_ranges, timing (ptalm_last_timing then reads
+ * the spin kernel's device time) and reduction (0: the default form, 1: both
+ * spins in one wavefront, 4 reals reduced per l; 2: one spin per wavefront,
+ * 2 reals per l, twice the wavefronts; else PTALM_EINVAL); precision must be
+ * PTALM_FP64 and n_weights 0 or 1 (else PTALM_ENOTSUP).  Allocates and frees stream-ordered scratch of
  * ptalm_shear_workspace_bytes(n, lmax, opts) bytes; builds the spin tables for
  * lmax on first use (synchronously).  Deterministic: the same inputs give the
  * same bits.  PTALM_EINVAL on bad sizes or pointers.

@@ -618,11 +618,17 @@ int get_spin_tables(int lmax, const ptalm::SpinTables **out) {
     return PTALM_OK;
 }
 
+// Default spin kernels: two spins per wavefront (reduction option 1) and one spin per
+// wavefront (option 2); kSpinSingle picks the default form.
 constexpr int kSpinKP = 4;
 constexpr int kSpinLB = 8;
+constexpr int kSpinSingleKP = 6;
+constexpr int kSpinSingleLB = 8;
+constexpr bool kSpinSingle = false;
 
 struct SpinResolved {
     int kp, lb, S, R;
+    bool single;
     int64_t groups;
 };
 
@@ -635,9 +641,11 @@ int spin_resolve(int64_t n, int lmax, const ptalm_opts *o, SpinResolved *r) {
     if (o->precision != PTALM_FP64) return fail(PTALM_ENOTSUP, "the shear transform is FP64 only");
     if (o->n_weights > 1) return fail(PTALM_ENOTSUP, "the shear transform takes one weight vector");
     if (o->n_slices > 65536) return fail(PTALM_EINVAL, "n_slices > 65536");
-    r->kp = o->points_per_lane ? o->points_per_lane : kSpinKP;
-    r->lb = o->l_block ? o->l_block : kSpinLB;
-    if (!ptalm::spin_variant_exists(r->kp, r->lb))
+    if (o->reduction < 0 || o->reduction > 2) return fail(PTALM_EINVAL, "shear reduction option must be 0, 1 or 2");
+    r->single = o->reduction ? o->reduction == 2 : kSpinSingle;
+    r->kp = o->points_per_lane ? o->points_per_lane : (r->single ? kSpinSingleKP : kSpinKP);
+    r->lb = o->l_block ? o->l_block : (r->single ? kSpinSingleLB : kSpinLB);
+    if (!ptalm::spin_variant_exists(r->kp, r->lb, r->single))
         return fail(PTALM_ENOTSUP, "no spin kernel variant with these points_per_lane / l_block");
     r->groups = (n + 64 * r->kp - 1) / (64 * r->kp);
     const int64_t gmax = std::max<int64_t>(1, r->groups);
@@ -714,7 +722,7 @@ int ptalm_shear_alm_from_points(const double *theta, const double *phi, const do
     a.partial = partial;
     bool supported = true;
     if (timed && (e = hipEventRecord(g_timing.start, stream)) != hipSuccess) return fail_hip(e, "hipEventRecord");
-    if ((e = ptalm::launch_spin(a, r.kp, r.lb, stream, &supported)) != hipSuccess) return fail_hip(e, "spin kernel launch");
+    if ((e = ptalm::launch_spin(a, r.kp, r.lb, r.single, stream, &supported)) != hipSuccess) return fail_hip(e, "spin kernel launch");
     if (!supported) return fail(PTALM_ENOTSUP, "spin kernel variant not compiled");
     if (timed) {
         if ((e = hipEventRecord(g_timing.stop, stream)) != hipSuccess) return fail_hip(e, "hipEventRecord");

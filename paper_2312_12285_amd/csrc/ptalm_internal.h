@@ -180,8 +180,8 @@ struct SpinArgs {
     double *partial;          // device, n_slices * 4T doubles
 };
 hipError_t build_spin_tables(int lmax, SpinTables *t, hipStream_t stream);
-bool spin_variant_exists(int kp, int lb);
-hipError_t launch_spin(const SpinArgs &a, int kp, int lb, hipStream_t stream, bool *supported);
+bool spin_variant_exists(int kp, int lb, bool single);
+hipError_t launch_spin(const SpinArgs &a, int kp, int lb, bool single, hipStream_t stream, bool *supported);
 hipError_t launch_spin_finish(const double *partial, int n_slices, const double *sigma, int lmax, double *alm_e,
                               double *alm_b, hipStream_t stream);
 

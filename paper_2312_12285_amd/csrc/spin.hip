@@ -330,6 +330,184 @@ __global__ __launch_bounds__(64) void spin_direct_kernel(SpinArgs args) {
     }
 }
 
+// One spin per wavefront.  Items (slice, range, spin) with the spin fastest, so the
+// two wavefronts of one (slice, range) run side by side over the same points and step
+// pairs.  A wavefront carries one chain per point and reduces 2 reals per l (its spin's
+// re and im) into its half of the 4 reals per (l, m) of the partial, so per term it
+// does half the two-spin kernel's cross-lane work and has the registers for more
+// points per lane.  Per point and step: the step factor, the chain and two
+// accumulations (4 FMAs); the lane values are those of the two-spin kernel.
+template <int KP, int LB, int SGN>
+__device__ __forceinline__ void spin_single_body(const SpinArgs &args, int r, int s, double *red) {
+    constexpr int V = 2 * LB;  // values reduced per l-block: (re, im) of this spin per l
+    using R = Red<V, 1>;
+    constexpr int P = R::P;
+    constexpr int RESCALE_EVERY = ChainRange<double>::every_l / LB;
+    constexpr double kAbove = ChainRange<double>::above;
+    constexpr int OFF = SGN > 0 ? 0 : 2;  // this spin's (re, im) within the 4 reals per (l, m)
+
+    const int lane = threadIdx.x;
+    const int lmax = args.lmax;
+    const int m_a = __builtin_amdgcn_readfirstlane(args.range_m[r]);
+    const int m_b = __builtin_amdgcn_readfirstlane(args.range_m[r + 1]);
+    const const_ptr<double> coef = (const_ptr<double>)(const void *)args.coef;
+    const int64_t g_a = (int64_t)s * args.groups / args.n_slices;
+    const int64_t g_b = (int64_t)(s + 1) * args.groups / args.n_slices;
+    double *part = args.partial + (int64_t)s * 4 * tri_size(lmax);
+    const int v = lane / P;
+    const int h = lane % P;
+
+    for (int64_t g = g_a; g < g_b; ++g) {
+        const bool first = (g == g_a);
+        double x[KP], ur[KP], ui[KP], s2[KP], c2[KP], Zr[KP], Zi[KP], gr[KP], gi[KP];
+        int Ze[KP];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) {
+            const int64_t i = g * (64 * KP) + t * 64 + lane;
+            double th = 1.5707963267948966, ph = 0.0, ww = 0.0, a1 = 0.0, a2 = 0.0;
+            if (i < args.n) {
+                th = args.theta[i];
+                ph = args.phi[i];
+                ww = args.w[i];
+                a1 = args.g1[i];
+                a2 = args.g2[i];
+            }
+            gr[t] = a1;
+            gi[t] = a2;
+            spin_point_seed(th, ph, ww, m_a, x[t], ur[t], ui[t], s2[t], c2[t], Zr[t], Zi[t], Ze[t]);
+        }
+
+        for (int m = m_a; m < m_b; ++m) {
+            if (m == 2 && m_a < 2) {
+#pragma unroll
+                for (int t = 0; t < KP; ++t) {
+                    const int64_t i = g * (64 * KP) + t * 64 + lane;
+                    double th = 1.5707963267948966, ph = 0.0, ww = 0.0;
+                    if (i < args.n) {
+                        th = args.theta[i];
+                        ph = args.phi[i];
+                        ww = args.w[i];
+                    }
+                    spin_point_seed(th, ph, ww, 2, x[t], ur[t], ui[t], s2[t], c2[t], Zr[t], Zi[t], Ze[t]);
+                }
+            }
+            const int L = lmax - m + 1;
+            const int j0 = (m >= 2) ? 0 : 2 - m;
+            const const_ptr<double> cm = coef + 2 * coef_segment(lmax, m);
+            double *pm = part + 4 * column_start(lmax, m) + OFF;
+
+            double E[KP], Ep[KP], Wr[KP], Wi[KP];
+            int q[KP];
+#pragma unroll
+            for (int t = 0; t < KP; ++t) {
+                double sv;
+                if (m == 0) sv = 4.0 * s2[t] * c2[t];
+                else if (m == 1) sv = SGN > 0 ? s2[t] : -c2[t];
+                else sv = SGN > 0 ? s2[t] * s2[t] : c2[t] * c2[t];
+                E[t] = 0.0;
+                Ep[t] = -sv;
+                q[t] = Ze[t];
+                const double zr = ldexp_t(Zr[t], q[t]), zi = ldexp_t(Zi[t], q[t]);
+                // W+ = Z G, W- = Z conj(G)
+                Wr[t] = SGN > 0 ? zr * gr[t] - zi * gi[t] : zr * gr[t] + zi * gi[t];
+                Wi[t] = SGN > 0 ? zr * gi[t] + zi * gr[t] : zi * gr[t] - zr * gi[t];
+            }
+
+            bool pending = false;
+            bool p_owner = false;
+            double *p_dst = pm;
+            double p_prev = 0.0;
+            int cur = 0;
+            int blk = 0;
+            for (int jb = j0; jb < L; jb += LB, ++blk) {
+                const bool owner = (h == 0) && (jb + (v >> 1) < L);
+                double *dst = pm + 4 * (jb + (v >> 1)) + (v & 1);
+                double prev = 0.0;
+                if (owner && !first) prev = *dst;
+                double ca[LB], cb[LB];
+#pragma unroll
+                for (int k = 0; k < LB; ++k) {
+                    ca[k] = cm[2 * (jb + k)];
+                    cb[k] = SGN > 0 ? cm[2 * (jb + k) + 1] : -cm[2 * (jb + k) + 1];
+                }
+                double vals[V];
+#pragma unroll
+                for (int k = 0; k < LB; ++k) {
+                    double re = 0.0, im = 0.0;
+#pragma unroll
+                    for (int t = 0; t < KP; ++t) {
+                        const double f = fma(ca[k], x[t], cb[k]);
+                        const double e = fma(f, E[t], -Ep[t]);
+                        Ep[t] = E[t];
+                        E[t] = e;
+                        re = fma(e, Wr[t], re);
+                        im = fma(e, Wi[t], im);
+                    }
+                    vals[2 * k] = re;
+                    vals[2 * k + 1] = im;
+                }
+                if (pending) {
+                    wave_lds_sync();
+                    const double sum = reduce_finish<double, V, 1>(red + (cur ^ 1) * R::BUF, v, h);
+                    if (p_owner) *p_dst = p_prev + sum;
+                }
+                reduce_write<double, V, 1>(red + cur * R::BUF, vals, lane);
+                pending = true;
+                p_owner = owner;
+                p_dst = dst;
+                p_prev = prev;
+                cur ^= 1;
+
+                if ((blk % RESCALE_EVERY) == RESCALE_EVERY - 1) {
+                    bool big = false;
+#pragma unroll
+                    for (int t = 0; t < KP; ++t) big |= fmax(fabs(E[t]), fabs(Ep[t])) > kAbove;
+                    if (__any(big)) {
+#pragma unroll
+                        for (int t = 0; t < KP; ++t) {
+                            const double mx = fmax(fabs(E[t]), fabs(Ep[t]));
+                            const int e = (mx > kAbove) ? frexp_exp_t(mx) : 0;
+                            E[t] = ldexp_t(E[t], -e);
+                            Ep[t] = ldexp_t(Ep[t], -e);
+                            q[t] += e;
+                            const double zr = ldexp_t(Zr[t], q[t]), zi = ldexp_t(Zi[t], q[t]);
+                            Wr[t] = SGN > 0 ? zr * gr[t] - zi * gi[t] : zr * gr[t] + zi * gi[t];
+                            Wi[t] = SGN > 0 ? zr * gi[t] + zi * gr[t] : zi * gr[t] - zr * gi[t];
+                        }
+                    }
+                }
+            }
+            if (pending) {
+                wave_lds_sync();
+                const double sum = reduce_finish<double, V, 1>(red + (cur ^ 1) * R::BUF, v, h);
+                if (p_owner) *p_dst = p_prev + sum;
+                wave_lds_sync();
+            }
+#pragma unroll
+            for (int t = 0; t < KP; ++t) {
+                const double tr = Zr[t] * ur[t] - Zi[t] * ui[t];
+                const double ti = Zr[t] * ui[t] + Zi[t] * ur[t];
+                Zr[t] = tr;
+                Zi[t] = ti;
+                renorm(Zr[t], Zi[t], Ze[t]);
+            }
+        }
+    }
+}
+
+template <int KP, int LB>
+__global__ __launch_bounds__(64) void spin_single_kernel(SpinArgs args) {
+    static_assert(LB % 2 == 0 && 64 % (2 * LB) == 0 && 2 * LB >= 16, "2*LB must divide 64, LB >= 8");
+    __shared__ double red[2 * Red<2 * LB, 1>::BUF];
+    const int item = (int)(blockIdx.x >> 1);
+    const int r = item % args.n_ranges;
+    const int s = item / args.n_ranges;
+    if (blockIdx.x & 1u)
+        spin_single_body<KP, LB, -1>(args, r, s, red);
+    else
+        spin_single_body<KP, LB, 1>(args, r, s, red);
+}
+
 // E = -sigma (S+ + S-) / 2, B = i sigma (S+ - S-) / 2 with S+-, the slice sums in
 // slice order; entries with sigma = 0 (l < 2) are written as 0 without reading
 // the partials (never written for them).
@@ -360,22 +538,40 @@ hipError_t launch_spin_one(const SpinArgs &a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int KP, int LB>
+hipError_t launch_spin_single(const SpinArgs &a, hipStream_t stream) {
+    const int blocks = 2 * a.n_ranges * a.n_slices;
+    hipLaunchKernelGGL((spin_single_kernel<KP, LB>), dim3(blocks), dim3(64), 0, stream, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 #define PTALM_SPIN_VARIANTS(X) X(4, 8) X(3, 8) X(2, 8) X(4, 16) X(3, 16) X(5, 8) X(6, 4) X(4, 4)
+#define PTALM_SPIN_SINGLE_VARIANTS(X) X(4, 8) X(5, 8) X(6, 8) X(7, 8) X(8, 8) X(4, 16) X(5, 16) X(6, 16)
 
-bool spin_variant_exists(int kp, int lb) {
+bool spin_variant_exists(int kp, int lb, bool single) {
 #define X(K, L) if (kp == K && lb == L) return true;
-    PTALM_SPIN_VARIANTS(X)
+    if (single) {
+        PTALM_SPIN_SINGLE_VARIANTS(X)
+    } else {
+        PTALM_SPIN_VARIANTS(X)
+    }
 #undef X
     return false;
 }
 
-hipError_t launch_spin(const SpinArgs &a, int kp, int lb, hipStream_t stream, bool *supported) {
+hipError_t launch_spin(const SpinArgs &a, int kp, int lb, bool single, hipStream_t stream, bool *supported) {
     *supported = true;
-#define X(K, L) if (kp == K && lb == L) return launch_spin_one<K, L>(a, stream);
-    PTALM_SPIN_VARIANTS(X)
+    if (single) {
+#define X(K, L) if (kp == K && lb == L) return launch_spin_single<K, L>(a, stream);
+        PTALM_SPIN_SINGLE_VARIANTS(X)
 #undef X
+    } else {
+#define X(K, L) if (kp == K && lb == L) return launch_spin_one<K, L>(a, stream);
+        PTALM_SPIN_VARIANTS(X)
+#undef X
+    }
     *supported = false;
     return hipSuccess;
 }

@@ -147,6 +147,10 @@ def test_shear_workspace_bytes(lib):
     assert f(1000, 64, ctypes.byref(_Opts(0, 2, 0, 0, 0, 0, 0, 0))) == 0          # one weight vector
     assert f(1000, 64, ctypes.byref(_Opts(0, 0, 9, 8, 0, 0, 0, 0))) == 0          # no such variant
     assert f(-1, 64, None) == 0 and f(10, 16384, None) == 0
+    o = _Opts(0, 0, 6, 8, 0, 0, 2, 0)                                               # one spin per wavefront
+    assert f(1000, 64, ctypes.byref(o)) == 8 * 4 * T(64) * min(32, (1000 + 383) // 384)
+    assert f(1000, 64, ctypes.byref(_Opts(0, 0, 6, 8, 0, 0, 1, 0))) == 0          # no two-spin (6, 8)
+    assert f(1000, 64, ctypes.byref(_Opts(0, 0, 0, 0, 0, 0, 3, 0))) == 0          # no such form
 
 
 def test_spline_rejects_point_counts_above_its_counters(lib):

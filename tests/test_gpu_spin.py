@@ -116,6 +116,49 @@ def test_variants_and_slices_agree(lib):
             assert max(err_e[2:].max(), err_b[2:].max()) <= 1e-12
 
 
+SINGLE_VARIANTS = [(4, 8), (5, 8), (6, 8), (7, 8), (8, 8), (4, 16), (5, 16), (6, 16)]
+
+
+@pytest.mark.parametrize("kp,lb", SINGLE_VARIANTS)
+def test_single_spin_form(lib, kp, lb):
+    """One spin per wavefront (reduction option 2): ragged point count, partial l-blocks and
+    polar points against the oracle; the two-spin form to rounding; E and B exactly real at
+    m = 0 (the two spins' wavefronts run the same operations there)."""
+    from oracle import spin
+    t, p, w, g1, g2 = catalog(5_003, 51, True)
+    lmax = 133
+    print(f"single-spin variant kp {kp} lb {lb}", flush=True)
+    args = [dev(a) for a in (t, p, w, g1, g2)]
+    o = lib.opts(points_per_lane=kp, l_block=lb, reduction=2)
+    e, b = [cplx(x) for x in lib.shear_alm_from_points(*args, lmax, options=o)]
+    we, wb = spin.shear_eb(t, p, w, g1, g2, lmax)
+    err = check(e, b, we, wb, lmax)
+    print(f"  per-l max rel err against the oracle {err:.3e}", flush=True)
+    e2, b2 = [cplx(x) for x in lib.shear_alm_from_points(*args, lmax, options=lib.opts(reduction=1))]
+    assert max(per_l(e, e2, lmax)[0][2:].max(), per_l(b, b2, lmax)[0][2:].max()) <= 1e-12
+    assert np.all(e[: lmax + 1].imag == 0.0) and np.all(b[: lmax + 1].imag == 0.0)
+
+
+def test_single_spin_near_poles_high_l(lib):
+    """The one-spin form on the near-pole catalog at lmax 600 (chain rescaling per spin)."""
+    from oracle import spin
+    rng = np.random.default_rng(12)
+    n = 300
+    d = np.abs(rng.normal(0, 0.003, n))
+    t = np.where(rng.random(n) < 0.5, d, math.pi - d)
+    t[:20] = np.arccos(rng.uniform(-1, 1, 20))
+    p = rng.uniform(0, 2 * math.pi, n)
+    w = rng.lognormal(0, 0.3, n)
+    g1, g2 = rng.normal(0, 0.26, n), rng.normal(0, 0.26, n)
+    lmax = 600
+    print(f"single-spin near-pole parity n {n} lmax {lmax}", flush=True)
+    o = lib.opts(reduction=2)
+    e, b = lib.shear_alm_from_points(dev(t), dev(p), dev(w), dev(g1), dev(g2), lmax, options=o)
+    we, wb = spin.shear_eb(t, p, w, g1, g2, lmax)
+    err = check(cplx(e), cplx(b), we, wb, lmax)
+    print(f"  per-l max rel err {err:.3e}", flush=True)
+
+
 def test_repeatable_and_eb_rotation(lib):
     """Bitwise repeatable; rotating every shear by 45 degrees (g -> i g) maps (E, B) to (-B, E)."""
     t, p, w, g1, g2 = catalog(6_000, 31)
@@ -143,6 +186,10 @@ def test_empty_tiny_and_arguments(lib):
         lib.shear_alm_from_points(*a, 10, options=lib.opts(precision=lib.MIXED))
     with pytest.raises(lib.PtalmError):
         lib.shear_alm_from_points(*a, 10, options=lib.opts(points_per_lane=9, l_block=8))
+    with pytest.raises(lib.PtalmError):
+        lib.shear_alm_from_points(*a, 10, options=lib.opts(points_per_lane=9, l_block=8, reduction=2))
+    with pytest.raises(lib.PtalmError):
+        lib.shear_alm_from_points(*a, 10, options=lib.opts(reduction=3))
     with pytest.raises(lib.PtalmError):
         lib.shear_alm_from_points(*a, 16384)
     with pytest.raises(ValueError):
