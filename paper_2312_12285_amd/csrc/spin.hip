@@ -35,7 +35,9 @@
 // order into the slice's partial column; a finishing kernel sums the slices in
 // order, applies sigma and forms E and B.  Per term (point, l, m) the inner loop
 // issues 8 FP64 FMAs: 2 for the two step factors, 2 for the two chains, 4 for
-// the complex accumulations.
+// the complex accumulations.  A second form runs one spin per wavefront
+// (twice the wavefronts, 2 reals per l reduced, 4 FMAs per point and step); the
+// host picks the form.
 #include "ptalm_internal.h"
 #include "wave_common.h"
 
