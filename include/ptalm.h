@@ -122,17 +122,20 @@ size_t ptalm_workspace_bytes(int64_t n, int lmax, const ptalm_opts *opts);
  * Pseudo-spectrum C_l = (2l+1)^-1 sum_{m=-l..l} |a_lm|^2 (eq. pseudoCl), the m<0
  * half by the symmetry a_{l,-m} = (-1)^m conj(a_lm).
  *   alm : 2*T doubles (input);  cl : lmax+1 doubles (output).
+ * PTALM_EINVAL as above, or cl overlapping alm.
  */
 int ptalm_cl_from_alm(const double *alm, int lmax, double *cl, void *stream);
 
 /*
  * Cross spectrum C^AB_l = (2l+1)^-1 sum_{m=-l..l} Re(a_lm conj(b_lm)), the
  * generalisation of eq. pseudoCl to two fields (Sec. 1, Sec. 4).
- *   alm1, alm2 : 2*T doubles each;  cl : lmax+1 doubles.
+ *   alm1, alm2 : 2*T doubles each (alm1 == alm2 gives the auto-spectrum);
+ *   cl : lmax+1 doubles.  PTALM_EINVAL as above, or cl overlapping an input.
  */
 int ptalm_cross_cl(const double *alm1, const double *alm2, int lmax, double *cl, void *stream);
 
-/* y <- y + alpha * x over 2*T doubles (x, y device; alpha host). */
+/* y <- y + alpha * x over 2*T doubles (x, y device; alpha host).  x == y is allowed;
+ * PTALM_EINVAL for other overlaps of x and y. */
 int ptalm_alm_axpy(double alpha, const double *x, double *y, int lmax, void *stream);
 
 /*

@@ -242,6 +242,13 @@ size_t multi_bytes(const Resolved &r, int64_t n, int lmax) {
     return multi_partial_bytes(r, lmax) + align256(sizeof(float) * (size_t)n * (size_t)r.n_weights);
 }
 
+// True when the n1 doubles at a and the n2 doubles at b share memory.
+bool overlaps(const double *a, int64_t n1, const double *b, int64_t n2) {
+    const uintptr_t a0 = (uintptr_t)a, a1 = a0 + sizeof(double) * (uintptr_t)n1;
+    const uintptr_t b0 = (uintptr_t)b, b1 = b0 + sizeof(double) * (uintptr_t)n2;
+    return a0 < b1 && b0 < a1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -398,6 +405,7 @@ int ptalm_cl_from_alm(const double *alm, int lmax, double *cl, void *stream) {
     g_error.clear();
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
     if (alm == nullptr || cl == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    if (overlaps(cl, lmax + 1, alm, 2 * ptalm::tri_size(lmax))) return fail(PTALM_EINVAL, "cl overlaps alm");
     hipError_t e = ptalm::launch_cl(alm, nullptr, lmax, cl, (hipStream_t)stream);
     return e == hipSuccess ? PTALM_OK : fail_hip(e, "cl kernel launch");
 }
@@ -406,6 +414,8 @@ int ptalm_cross_cl(const double *alm1, const double *alm2, int lmax, double *cl,
     g_error.clear();
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
     if (alm1 == nullptr || alm2 == nullptr || cl == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    if (overlaps(cl, lmax + 1, alm1, 2 * ptalm::tri_size(lmax)) || overlaps(cl, lmax + 1, alm2, 2 * ptalm::tri_size(lmax)))
+        return fail(PTALM_EINVAL, "cl overlaps an input");
     hipError_t e = ptalm::launch_cl(alm1, alm2, lmax, cl, (hipStream_t)stream);
     return e == hipSuccess ? PTALM_OK : fail_hip(e, "cross_cl kernel launch");
 }
@@ -414,6 +424,8 @@ int ptalm_alm_axpy(double alpha, const double *x, double *y, int lmax, void *str
     g_error.clear();
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
     if (x == nullptr || y == nullptr) return fail(PTALM_EINVAL, "NULL pointer");
+    if (x != y && overlaps(x, 2 * ptalm::tri_size(lmax), y, 2 * ptalm::tri_size(lmax)))
+        return fail(PTALM_EINVAL, "x and y overlap without being the same array");
     hipError_t e = ptalm::launch_axpy(alpha, x, y, 2 * ptalm::tri_size(lmax), (hipStream_t)stream);
     return e == hipSuccess ? PTALM_OK : fail_hip(e, "axpy kernel launch");
 }

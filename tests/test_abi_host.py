@@ -167,3 +167,18 @@ def test_spline_rejects_point_counts_above_its_counters(lib):
     assert f(fake, fake, fake, -1, 64, 100, 0.01, fake, None, None) == -1
     assert f(fake, fake, fake, 10, 64, 1, 0.01, fake, None, None) == -1           # n_nodes < 2
     assert f(fake, fake, fake, 10, 64, 100, 2.0, fake, None, None) == -1          # theta_cut >= pi/2
+
+
+def test_spectra_and_axpy_reject_overlapping_outputs(lib):
+    """Overlap checks return before any device call (fake device pointers)."""
+    vp = ctypes.c_void_p
+    lib.ptalm_cl_from_alm.argtypes = [vp, ctypes.c_int, vp, vp]
+    lib.ptalm_cross_cl.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+    lib.ptalm_alm_axpy.argtypes = [ctypes.c_double, vp, vp, ctypes.c_int, vp]
+    lmax = 10
+    nbytes = 8 * 2 * (lmax + 1) * (lmax + 2) // 2
+    a = 1 << 40
+    assert lib.ptalm_cl_from_alm(a, lmax, a + nbytes - 8, None) == -1          # cl starts inside alm
+    assert lib.ptalm_cl_from_alm(a, lmax, a - 8, None) == -1                   # cl runs into alm
+    assert lib.ptalm_cross_cl(a, a + 2 * nbytes, lmax, a + 2 * nbytes + 64, None) == -1
+    assert lib.ptalm_alm_axpy(1.0, a, a + 16, lmax, None) == -1                # shifted overlap
