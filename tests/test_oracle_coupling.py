@@ -157,3 +157,4 @@ def test_coupling_rows_match_full_matrix(oracle):
     assert np.array_equal(oracle.coupling_rows(W, 60, rows), M[rows])
     with pytest.raises(ValueError):
         oracle.coupling_rows(W, 60, [61])
+

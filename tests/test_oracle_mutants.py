@@ -101,6 +101,14 @@ COUPLING_MUTANTS = {
     "coupling_wrong_degree_factor": ("(double)((2.0L * lp + 1.0L) * inv4pi * sum)", "(double)((2.0L * l + 1.0L) * inv4pi * sum)"),
     "coupling_lambda_range_short": ("const int hi = l + lp < lmax_w ? l + lp : lmax_w;",
                                     "const int hi = l + lp < lmax_w ? l + lp : lmax_w - 1;"),
+    "coupling_first_lambda_dropped": ("for (int lam = lo; lam <= hi; lam += 2) {",
+                                      "for (int lam = lo + 2; lam <= hi; lam += 2) {"),
+    "coupling_window_index_shifted": ("sum += (2.0L * lam + 1.0L) * t * t * (long double)Wl[lam];",
+                                      "sum += (2.0L * lam + 1.0L) * t * t * (long double)Wl[lam > 0 ? lam - 1 : 0];"),
+    "coupling_two_pi": ("const long double inv4pi = 1.0L / (4.0L * 3.14159265358979323846264338327950288L);",
+                        "const long double inv4pi = 1.0L / (2.0L * 3.14159265358979323846264338327950288L);"),
+    "threej_factorial_index": ("lfact(h) - lfact(h - l1) - lfact(h - l2) - lfact(h - l3);",
+                               "lfact(h) - lfact(h - l1) - lfact(h - l1) - lfact(h - l3);"),
 }
 
 
