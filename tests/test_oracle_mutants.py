@@ -143,3 +143,37 @@ def test_planted_coupling_mistake_is_caught(name, tmp_path):
                     str(tmp_path / "ptalm_ref.c"), "-lm"], check=True)
     with ref.use_library(str(so)):
         assert not run_coupling_pins(), f"planted mistake {name!r} passed every coupling pin"
+
+
+# Planted mistakes in the oracle's bandpower algebra (plain numpy): each replaces one
+# statement of a function of oracle/ref.py for the duration of the test.
+BANDPOWER_MUTANTS = {
+    "coupled_bins_averaged_twice": ("decoupled_bandpowers", "Mbb = theta @ M @ chi", "Mbb = theta @ M @ theta.T"),
+    "bandpowers_not_decoupled": ("decoupled_bandpowers", "cb = np.linalg.solve(Mbb, theta @ np.asarray(cl_hat))",
+                                 "cb = theta @ np.asarray(cl_hat)"),
+    "window_not_decoupled": ("decoupled_bandpowers", "window = np.linalg.solve(Mbb, theta @ M)", "window = theta @ M"),
+    "normalisation_two_pi": ("normalized_bandpowers", "(2 * lam + 1) / (4 * np.pi) * Wl", "(2 * lam + 1) / (2 * np.pi) * Wl"),
+    "normalisation_weight": ("normalized_bandpowers", "(2 * lam + 1) / (4 * np.pi) * Wl", "(2 * lam) / (4 * np.pi) * Wl"),
+    "bin_weight_not_averaged": ("bin_matrix", "theta[b, lo:lo + delta_l] = 1.0 / delta_l", "theta[b, lo:lo + delta_l] = 1.0"),
+    "bin_one_short": ("bin_matrix", "theta[b, lo:lo + delta_l] = 1.0 / delta_l",
+                      "theta[b, lo:lo + delta_l - 1] = 1.0 / delta_l"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BANDPOWER_MUTANTS))
+def test_planted_bandpower_mistake_is_caught(name, monkeypatch):
+    import inspect
+    import test_oracle_coupling as t
+    fn, old, new = BANDPOWER_MUTANTS[name]
+    src = inspect.getsource(getattr(ref, fn))
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    ns = dict(ref.__dict__)
+    exec(src.replace(old, new), ns)
+    monkeypatch.setattr(ref, fn, ns[fn])
+    with pytest.raises(AssertionError):
+        t.test_bandpowers_recover_piecewise_constant_and_shot_noise(ref)
+
+
+def test_real_oracle_passes_bandpower_pin():
+    import test_oracle_coupling as t
+    t.test_bandpowers_recover_piecewise_constant_and_shot_noise(ref)
