@@ -93,6 +93,8 @@ TRAFFIC_SOURCES = {
     "randoms3072": (["alm_direct.hip", "wave_common.h"],
                     ("api.hip", "// Default kernel variant and decomposition.", "size_t align256(size_t b)")),
     "spline3072": (["spline.hip", "wave_common.h"], None),
+    "multi2048": (["alm_multi.hip"],
+                  ("api.hip", "// Default kernel variant and decomposition.", "size_t align256(size_t b)")),
 }
 
 
@@ -282,7 +284,9 @@ def run_multi(args, cats, lmax):
     useful = MULTI_FLOPS_PER_TERM * weight_terms
     achieved = useful / (step_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(args.workload if args.scale == 1.0 else None,
+                                            f"bf16x3,nw={nw},S={best.n_slices}"),
                 "kernel": "alm_multi_kernel<32>", "kernel_ms_per_launch": round(step_ms, 3),
                 "timed_span": "whole replayed graph (transform + 32 spectra), events on the replay stream",
                 "flops_per_weight_term": MULTI_FLOPS_PER_TERM, "issued_mfma_flops_per_useful": 3}
