@@ -93,6 +93,9 @@ TRAFFIC_SOURCES = {
     "randoms3072": (["alm_direct.hip", "wave_common.h"],
                     ("api.hip", "// Default kernel variant and decomposition.", "size_t align256(size_t b)")),
     "spline3072": (["spline.hip", "wave_common.h"], None),
+    "shear3072": (["spin.hip", "wave_common.h"],
+                  ("api.hip", "// Default spin kernels:", "size_t ptalm_shear_workspace_bytes(")),
+    "coupling3072": (["coupling.hip"], None),
     "multi2048": (["alm_multi.hip"],
                   ("api.hip", "// Default kernel variant and decomposition.", "size_t align256(size_t b)")),
 }
@@ -452,7 +455,9 @@ def run_shear(args, cats, lmax):
     k_ms = float(np.mean(kernel_ms))
     achieved = SPIN_FLOPS_PER_TERM * terms / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(args.workload if args.scale == 1.0 else None,
+                                            f"kp={args.points_per_lane or 'default'},lb={args.l_block or 'default'}"),
                 "kernel": "spin_direct_kernel<4, 8>" if not (args.points_per_lane or args.l_block) else
                           f"spin_direct_kernel<{args.points_per_lane or 4}, {args.l_block or 8}>",
                 "kernel_ms_per_launch": round(k_ms, 3), "flops_per_term": SPIN_FLOPS_PER_TERM}
@@ -580,7 +585,8 @@ def run_coupling(args):
     flops = 2.0 * half_terms       # one multiply-add per term of the contraction, each unordered (l, l') once
     achieved = flops / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic(args.workload, "tables+mfma per call"),
                 "kernel": "coupling_tables_kernel + coupling_mfma_kernel (one ptalm_coupling_matrix call)",
                 "kernel_ms_per_launch": round(k_ms, 4), "flops_per_term": 2,
                 "terms_per_launch": half_terms}
