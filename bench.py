@@ -93,6 +93,7 @@ TRAFFIC_SOURCES = {
     "randoms3072": (["alm_direct.hip", "wave_common.h"],
                     ("api.hip", "// Default kernel variant and decomposition.", "size_t align256(size_t b)")),
     "spline3072": (["spline.hip", "wave_common.h"], None),
+    "spline1000": (["spline.hip", "wave_common.h"], None),
     "shear3072": (["spin.hip", "wave_common.h"],
                   ("api.hip", "// Default spin kernels:", "size_t ptalm_shear_workspace_bytes(")),
     "coupling3072": (["coupling.hip"], None),
