@@ -182,3 +182,21 @@ def test_spectra_and_axpy_reject_overlapping_outputs(lib):
     assert lib.ptalm_cl_from_alm(a, lmax, a - 8, None) == -1                   # cl runs into alm
     assert lib.ptalm_cross_cl(a, a + 2 * nbytes, lmax, a + 2 * nbytes + 64, None) == -1
     assert lib.ptalm_alm_axpy(1.0, a, a + 16, lmax, None) == -1                # shifted overlap
+
+
+def test_header_is_plain_c_and_cxx(tmp_path):
+    """include/ptalm.h compiles as C99 and as C++11 with no HIP or torch headers, and a C
+    translation unit that takes the address of every declared function links against it."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    subprocess.run(["gcc", "-fsyntax-only", "-std=c99", "-Wall", "-Werror", "-x", "c", HEADER], check=True)
+    subprocess.run(["g++", "-fsyntax-only", "-std=c++11", "-Wall", "-Werror", "-x", "c++", HEADER], check=True)
+    names = declared_functions()
+    src = tmp_path / "use.c"
+    src.write_text('#include "ptalm.h"\n#include <stdio.h>\nint main(void) {\n'
+                   + "".join(f'    printf("%p\\n", (void *)&{n});\n' for n in names) + "    return 0;\n}\n")
+    exe = tmp_path / "use"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe), LIB,
+                    f"-Wl,-rpath,{os.path.dirname(LIB)}"], check=True)
