@@ -27,7 +27,8 @@ Workloads (--workload):
   spline1000   the configuration the paper times its own method on (1e8 points, lmax ~1000,
                2048 nodes uniform in x, ~30 s on 4 A100s): 1e8 full-sky uniform points,
                lmax 1000, 3217 nodes uniform in theta (the same equatorial spacing), 1 deg
-               caps; vs_baseline = value / the paper's equivalent rate (1.7e12 terms/s)
+               caps; the paper's equivalent rate (1.7e12 terms/s on other hardware) is quoted
+               beside it as context, not as a baseline
   coupling3072 mode coupling and bandpowers from a window spectrum W_l (l <= 6144) and a
                pseudo-spectrum (l <= 3072): shot noise of 1e8 unit-weight randoms scaled by
                alpha, M_ll' (l, l' <= 3072) with the shot noise removed from W, decoupled
@@ -39,11 +40,21 @@ Workloads (--workload):
                the same trace time-scaled to 0.7x the measured capacity, and a
                burst of the first 100 requests served vs run one after another
 
-Besides value, the line carries the roofline of the transform kernel (its
-algorithmic FP64 work, 7 flops per term, over its device time measured with
-HIP events the library records on the launch stream), the CPU oracle timed on
-a bounded prefix of the same catalog, and a sampled parity check of the full
-result against oracle entries computed over every point.
+Besides value, the line carries the roofline of the transform kernel (the FP64
+work it executes, 6.5 flops per term, over its device time measured with HIP
+events the library records on the launch stream, and the fraction of VALU issue
+slots its 3.5 instructions per term fill), the CPU oracle timed on a bounded
+prefix of the same catalog, and a sampled parity check of the full result
+against oracle entries computed over every point.  The default workload adds
+one mixed-precision step on the same catalog (rate and error per l against the
+FP64 result) when the budget leaves room for it.
+
+Wall-clock budget: the whole run, from process start, is kept within
+--time-budget seconds (480 by default).  --steps and --warmup are upper
+limits: the first step measures a step's duration, the checks run after it,
+and only the warmup and timed steps that still fit are run (at least one
+timed).  The line reports the steps actually timed (steps, warmup) beside the
+requested ones (steps_requested, warmup_requested).
 """
 import argparse
 import json
@@ -52,13 +63,17 @@ import os
 import sys
 import time
 
+START = time.monotonic()      # the wall-clock budget counts from here (torch import and generation included)
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector peak (256 CUs x 2.4 GHz x 128 flop/clk/CU)
 BF16_PEAK_TFLOPS = 2500.0     # MI355X dense bf16 matrix peak
 MULTI_FLOPS_PER_TERM = 4      # per (point, l, m, weight vector): re and im multiply-adds
-FLOPS_PER_TERM = 7            # recurrence multiply + FMA, two accumulate FMAs
+FLOPS_PER_TERM = 6.5          # FP64 flops the direct kernel executes per term: 3 FMA + 0.5 MUL
+VALU_INSTS_PER_TERM = 3.5     # its FP64 VALU instructions per term (split recurrence 1.5, accumulate 2)
+VALU_ISSUE_PER_S = 256 * 2.4e9 * 64   # lane-instructions/s: 256 CUs, 4 SIMDs x 16 lanes, 2.4 GHz
 SPIN_FLOPS_PER_TERM = 16      # spin +-2: two step factors, two chains, four accumulate FMAs
 METRIC = "point\u00b7(l,m) terms/s FP64 vs mixed at stated rel err; served p50/p99 latency"
 UNIT = "point\u00b7(l,m) terms/s"
@@ -83,6 +98,83 @@ WORKLOADS = {
     "multi2048": dict(desc="one masked position set n=1e7 shared by 32 lognormal weight vectors (sigma=0.2), "
                            "lmax=2048, split-bf16 MFMA form", lmax=2048),
 }
+
+
+class Budget:
+    """Wall-clock budget of one bench run, counted from process start.  --steps and --warmup are
+    upper limits: a step whose measured duration no longer fits is not started."""
+
+    def __init__(self, seconds):
+        self.end = START + seconds
+
+    def left(self):
+        return self.end - time.monotonic()
+
+
+def run_steps(step, sync, warmup, steps, budget, reserve_s=0.0, after_first=None, label="step",
+              optional=None, min_timed_with_optional=2):
+    """Up to `warmup` untimed and `steps` timed steps, inside the budget, timed steps first.
+    The first step runs alone (synchronized) to measure a step's duration; `after_first`
+    (checks that read a finished step's output) runs right after it when that step is a
+    warmup.  Then the steps that still fit are shared out: timed steps first (at least one),
+    further warmups only with time to spare.  `reserve_s` seconds are kept free for work after
+    the timed steps, and, when optional = (k, s) is given, k step durations plus s seconds more
+    for an optional run after them if at least `min_timed_with_optional` timed steps still fit
+    beside it.  Returns a dict: warmup_done, steps (timed), elapsed_s (over the timed steps),
+    step_s (duration of one step), optional (whether that time was kept free)."""
+    done_w = 0
+    step_s = None
+    timed = 0
+    if warmup > 0:
+        print(f"[bench] warmup {label} 0", file=sys.stderr, flush=True)
+        t = time.monotonic()
+        step()
+        sync()
+        step_s = time.monotonic() - t
+        done_w = 1
+        if after_first is not None:
+            after_first()
+
+    def fitting(extra):
+        return int(max(0.0, budget.left() - reserve_s - extra) // (step_s * 1.05)) if step_s > 0 else steps + warmup
+
+    def optional_s():
+        return 0.0 if optional is None else optional[0] * step_s * 1.05 + optional[1]
+
+    sync()
+    t0 = time.perf_counter()
+    if step_s is None:          # no warmup: the first timed step measures the duration
+        step()
+        sync()
+        step_s = time.perf_counter() - t0
+        timed = 1
+        print(f"[bench] timed {label} 0 done ({step_s:.2f} s)", file=sys.stderr, flush=True)
+        n = max(0, min(steps - timed, fitting(0.0)))
+        keep_optional = optional is not None and timed + fitting(optional_s()) >= min_timed_with_optional
+        if keep_optional:
+            n = max(0, min(steps - timed, fitting(optional_s())))
+    else:
+        keep_optional = optional is not None and fitting(optional_s()) >= min_timed_with_optional
+        fit = fitting(optional_s() if keep_optional else 0.0)
+        n = max(1, min(steps, fit))
+        more_w = max(0, min(warmup - done_w, fit - n))
+        for _ in range(more_w):
+            print(f"[bench] warmup {label} {done_w}", file=sys.stderr, flush=True)
+            step()
+            done_w += 1
+        sync()
+        t0 = time.perf_counter()
+    if n > 0:
+        print(f"[bench] timing {n} {'more ' if timed else ''}{label}(s) ({timed + n} of {steps} requested fit the "
+              f"budget)", file=sys.stderr, flush=True)
+    for i in range(n):
+        step()
+    sync()
+    elapsed = time.perf_counter() - t0
+    timed += n
+    print(f"[bench] {timed} timed {label}(s) in {elapsed:.2f} s", file=sys.stderr, flush=True)
+    return {"warmup_done": done_w, "steps": timed, "elapsed_s": elapsed, "step_s": step_s,
+            "optional": keep_optional}
 
 
 PROFILES = os.path.join(HERE, "profiles")
@@ -270,21 +362,21 @@ def run_multi(args, cats, lmax):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         body()
-    for i in range(args.warmup):
+    evs = []
+
+    def step():
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         g.replay()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    print(f"[bench] timing {args.steps} graph replay(s)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record()
-        g.replay()
-        ev[i][1].record()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    step_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        b.record()
+        evs.append((a, b))
+
+    res = run_steps(step, torch.cuda.synchronize, args.warmup, args.steps, Budget(args.time_budget),
+                    reserve_s=30.0 + args.cpu_seconds, label="graph replay")
+    elapsed, steps = res["elapsed_s"], res["steps"]
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b in evs[res["warmup_done"]:]]))
     weight_terms = nw * n * T
-    value = weight_terms * args.steps / elapsed
+    value = weight_terms * steps / elapsed
     useful = MULTI_FLOPS_PER_TERM * weight_terms
     achieved = useful / (step_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -295,7 +387,8 @@ def run_multi(args, cats, lmax):
                 "timed_span": "whole replayed graph (transform + 32 spectra), events on the replay stream",
                 "flops_per_weight_term": MULTI_FLOPS_PER_TERM, "issued_mfma_flops_per_useful": 3}
     line = {"metric": METRIC, "value": value, "unit": UNIT + " (summed over the weight vectors)",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+            "n_gpus": 1, "steps": steps, "warmup": res["warmup_done"], "steps_requested": args.steps,
+            "warmup_requested": args.warmup, "ms_per_step": round(1e3 * elapsed / steps, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "bf16x3 split products, f32 accumulate, f64 recurrence", "data": "synthetic",
             "config": {"workload": WORKLOADS[args.workload]["desc"], "lmax": lmax, "points": n, "weight_vectors": nw,
@@ -337,25 +430,23 @@ def run_spline(args, cats, lmax):
     T = tri(lmax)
     out = torch.empty(2 * T, dtype=torch.float64, device="cuda")
     ptalm.prepare(lmax)     # the polar part's direct-sum tables, outside the timed region
-    for i in range(args.warmup):
-        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
-        ptalm.alm_from_points_spline(t, p, w, lmax, nodes, cut, out=out)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     opt = ptalm.opts(timing=1)
-    bin_ms = []
-    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record()
+    evs, bin_ms = [], []
+
+    def step():
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         ptalm.alm_from_points_spline(t, p, w, lmax, nodes, cut, out=out, options=opt)
-        ev[i][1].record()
+        b.record()
+        evs.append((a, b))
         bin_ms.append(ptalm.last_timing_ms())
-        cl = ptalm.cl_from_alm(out, lmax)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    call_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    k_ms = float(np.mean(bin_ms))
+        ptalm.cl_from_alm(out, lmax)
+
+    res = run_steps(step, torch.cuda.synchronize, args.warmup, args.steps, Budget(args.time_budget),
+                    reserve_s=90.0 + args.cpu_seconds)
+    elapsed, steps, wd = res["elapsed_s"], res["steps"], res["warmup_done"]
+    call_ms = float(np.mean([a.elapsed_time(b) for a, b in evs[wd:]]))
+    k_ms = float(np.mean(bin_ms[wd:]))
     theta = cat.theta
     n_polar = int(((theta < cut) | (theta > math.pi - cut)).sum())
     flops = SPLINE_FLOPS_PER_TERM * (n - n_polar) * (lmax + 1)
@@ -366,17 +457,18 @@ def run_spline(args, cats, lmax):
                 "kernel": "bin_kernel (per-m binned Hermite weights)", "kernel_ms_per_launch": round(k_ms, 3),
                 "flops_per_point_m": SPLINE_FLOPS_PER_TERM, "call_ms": round(call_ms, 3),
                 "call_tflops": round(flops / (call_ms * 1e-3) / 1e12, 3)}
-    line = {"metric": METRIC, "value": n * T * args.steps / elapsed, "unit": UNIT + " (of the exact sum replaced)",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+    line = {"metric": METRIC, "value": n * T * steps / elapsed, "unit": UNIT + " (of the exact sum replaced)",
+            "n_gpus": 1, "steps": steps, "warmup": wd, "steps_requested": args.steps,
+            "warmup_requested": args.warmup, "ms_per_step": round(1e3 * elapsed / steps, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": wl["desc"], "lmax": lmax, "points": n, "nodes": nodes,
                        "theta_cut_deg": SPLINE_CUT_DEG, "polar_points": n_polar},
             "roofline": roofline}
     if args.workload == "spline1000":
-        # the paper's own method on the configuration it is timed on (other hardware: context)
-        line["vs_baseline"] = round(line["value"] / PAPER_SHT_RATE, 2)
-        line["baseline"] = {"value": PAPER_SHT_RATE, "what": "the paper's interpolated transform, 1e8 points, "
-                            "lmax ~1000, 2048 nodes, ~30 s on 4 A100s, as the exact-sum rate it replaces"}
+        # the paper's own method on the configuration it is timed on: other hardware, so context only
+        line["paper_context"] = {"value": PAPER_SHT_RATE, "unit": UNIT + " (of the exact sum replaced)",
+                                 "what": "the paper's interpolated transform, 1e8 points, lmax ~1000, 2048 nodes, "
+                                         "~30 s on 4 A100s, as the exact-sum rate it replaces"}
     if not args.no_check:
         print("[bench] error vs the exact GPU sum on the first 2e6 points", file=sys.stderr, flush=True)
         k = min(n, 2_000_000)
@@ -440,20 +532,11 @@ def run_shear(args, cats, lmax):
         ptalm.cl_from_alm(b, lmax, out=cls[1])
         ptalm.cross_cl(e, b, lmax, out=cls[2])
 
-    for i in range(args.warmup):
-        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
-        step()
-    torch.cuda.synchronize()
-    kernel_ms.clear()
-    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    res = run_steps(step, torch.cuda.synchronize, args.warmup, args.steps, Budget(args.time_budget),
+                    reserve_s=40.0 + args.cpu_seconds)
+    elapsed, steps, wd = res["elapsed_s"], res["steps"], res["warmup_done"]
     terms = n * T
-    k_ms = float(np.mean(kernel_ms))
+    k_ms = float(np.mean(kernel_ms[wd:]))
     achieved = SPIN_FLOPS_PER_TERM * terms / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
@@ -462,8 +545,9 @@ def run_shear(args, cats, lmax):
                 "kernel": "spin_direct_kernel<4, 8>" if not (args.points_per_lane or args.l_block) else
                           f"spin_direct_kernel<{args.points_per_lane or 4}, {args.l_block or 8}>",
                 "kernel_ms_per_launch": round(k_ms, 3), "flops_per_term": SPIN_FLOPS_PER_TERM}
-    line = {"metric": METRIC, "value": terms * args.steps / elapsed, "unit": UNIT + " (spin +-2, both spins per term)",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+    line = {"metric": METRIC, "value": terms * steps / elapsed, "unit": UNIT + " (spin +-2, both spins per term)",
+            "n_gpus": 1, "steps": steps, "warmup": wd, "steps_requested": args.steps,
+            "warmup_requested": args.warmup, "ms_per_step": round(1e3 * elapsed / steps, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": WORKLOADS["shear3072"]["desc"], "lmax": lmax, "points": n, "terms_per_step": terms},
             "roofline": roofline}
@@ -571,18 +655,10 @@ def run_coupling(args):
         cbn, winn = ptalm.bandpowers(cld, M, lmax, COUPLING_DL, lmin=COUPLING_LMIN, mode=1, Wl=Wd)
         return cb, cbn
 
-    for i in range(args.warmup):
-        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
-        step()
-    torch.cuda.synchronize()
-    cms.clear()
-    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        cb, cbn = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in cms]))
+    res = run_steps(step, torch.cuda.synchronize, args.warmup, args.steps, Budget(args.time_budget),
+                    reserve_s=30.0 + args.cpu_seconds)
+    elapsed, steps, wd = res["elapsed_s"], res["steps"], res["warmup_done"]
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in cms[wd:]]))
     flops = 2.0 * half_terms       # one multiply-add per term of the contraction, each unordered (l, l') once
     achieved = flops / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -591,9 +667,10 @@ def run_coupling(args):
                 "kernel": "coupling_tables_kernel + coupling_mfma_kernel (one ptalm_coupling_matrix call)",
                 "kernel_ms_per_launch": round(k_ms, 4), "flops_per_term": 2,
                 "terms_per_launch": half_terms}
-    line = {"metric": "coupling-sum terms (l,l',lambda)/s, mode coupling + bandpowers", "value": terms * args.steps / elapsed,
-            "unit": "(l,l',lambda) terms/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+    line = {"metric": "coupling-sum terms (l,l',lambda)/s, mode coupling + bandpowers", "value": terms * steps / elapsed,
+            "unit": "(l,l',lambda) terms/s", "n_gpus": 1, "steps": steps, "warmup": wd,
+            "steps_requested": args.steps, "warmup_requested": args.warmup,
+            "ms_per_step": round(1e3 * elapsed / steps, 3), "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": WORKLOADS["coupling3072"]["desc"], "lmax": lmax, "lmax_w": lw,
                        "randoms": n_r, "delta_l": COUPLING_DL, "lmin": COUPLING_LMIN,
@@ -754,6 +831,11 @@ def main():
     ap.add_argument("--l-block", type=int, default=0)
     ap.add_argument("--scale", type=float, default=1.0, help="catalog size factor (1 = the named workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--time-budget", type=float, default=480.0,
+                    help="wall-clock seconds for the whole run from process start; --steps and --warmup are "
+                         "upper limits inside it (at least one step is timed)")
+    ap.add_argument("--no-mixed-record", dest="mixed_record", action="store_false",
+                    help="default workload: skip the extra mixed-precision step run when the budget has room")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--served-requests", type=int, default=500)
@@ -826,51 +908,94 @@ def main():
     # build the per-lmax tables outside the timed region
     ptalm.prepare(lmax)
     torch.cuda.synchronize()
-    for i in range(args.warmup):
-        print(f"[bench] warmup step {i}", file=sys.stderr, flush=True)
-        step()
-    torch.cuda.synchronize()
-    kernel_ms.clear()
-    print(f"[bench] timing {args.steps} step(s)", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    budget = Budget(args.time_budget)
+    line = {}
+    checks_done = []
+
+    def checks():
+        """Parity and the CPU baseline read a finished step's output (every step computes the
+        same result bitwise), so they run after the first warmup, before the timed steps."""
+        if not args.no_check:
+            print("[bench] sampled parity against oracle entries", file=sys.stderr, flush=True)
+            line["parity"] = sampled_parity(cats[-1][1], lmax, outs[-1])
+            if prec != ptalm.FP64:
+                print("[bench] precision error against the FP64 path and the oracle", file=sys.stderr, flush=True)
+                line["precision_error"] = precision_errors(args, cats[-1][1], lmax, outs[-1], prec)
+        if not args.no_cpu_baseline:
+            print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = cpu_baseline(cats, lmax, min(args.cpu_seconds, max(2.0, budget.left() / 8)))
+        checks_done.append(True)
+
+    # parity (8 oracle entries over every point) and the CPU baseline, if they still run after the
+    # timed steps (no warmup requested): ~30 s per 1e8 points + the baseline sample
+    reserve = 0.0 if args.warmup > 0 else (3e-7 * sum(n for *_, n in dev) + args.cpu_seconds + 10.0)
+    want_mixed = args.precision == "fp64" and args.mixed_record and args.scale == 1.0 and len(dev) == 1
+    res = run_steps(step, torch.cuda.synchronize, args.warmup, args.steps, budget,
+                    reserve_s=reserve + 10.0, after_first=checks if args.warmup > 0 else None,
+                    label="step", optional=(1.0, 15.0) if want_mixed else None)
+    if not checks_done:
+        kernel_ms_timed = list(kernel_ms)
+        checks()
+    else:
+        kernel_ms_timed = kernel_ms[res["warmup_done"]:]
+    elapsed = res["elapsed_s"]
+    steps = res["steps"]
 
     terms_per_step = sum(n for *_, n in dev) * T
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = terms_per_step * args.steps / elapsed
-    k_ms = float(np.mean(kernel_ms)) / len(dev)           # average transform-kernel launch
-    flops_per_launch = FLOPS_PER_TERM * terms_per_step / len(dev)
-    achieved = flops_per_launch / (k_ms * 1e-3) / 1e12
+    ms_per_step = 1e3 * elapsed / steps
+    value = terms_per_step * steps / elapsed
+    k_ms = float(np.mean(kernel_ms_timed[:steps])) / len(dev)     # average transform-kernel launch
+    launch_terms = terms_per_step / len(dev)
+    achieved = FLOPS_PER_TERM * launch_terms / (k_ms * 1e-3) / 1e12
     variant = f"kp={args.points_per_lane or 'default'},lb={args.l_block or 'default'},{args.precision}"
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": recorded_traffic(args.workload if args.scale == 1.0 else None, variant),
                 "kernel": "alm_direct_kernel<" + {"fp64": "double, double", "mixed": "double, float",
                                                   "fp32": "float, float"}[args.precision] + ", ...>",
-                "kernel_ms_per_launch": round(k_ms, 3), "flops_per_term": FLOPS_PER_TERM}
+                "kernel_ms_per_launch": round(k_ms, 3), "flops_per_term": FLOPS_PER_TERM,
+                "flops_per_term_note": "executed: 3 FMA + 0.5 MUL per term (split recurrence + two accumulates)",
+                "valu_issue_frac": round(VALU_INSTS_PER_TERM * launch_terms / (k_ms * 1e-3) / VALU_ISSUE_PER_S, 4)}
 
-    line = {"metric": METRIC, "value": value, "unit": UNIT,
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": {"fp64": "f64", "mixed": "f64 recurrence + f32 products", "fp32": "f32 + f64"}[args.precision], "data": "synthetic",
-            "config": {"workload": wl["desc"], "lmax": lmax, "points": sum(n for *_, n in dev),
-                       "terms_per_step": terms_per_step, "precision": args.precision,
-                       "points_per_lane": args.points_per_lane or "default", "l_block": args.l_block or "default"},
-            "roofline": roofline}
-    if not args.no_check:
-        print("[bench] sampled parity against oracle entries", file=sys.stderr, flush=True)
-        line["parity"] = sampled_parity(cats[-1][1], lmax, outs[-1])
-        if prec != ptalm.FP64:
-            print("[bench] precision error against the FP64 path and the oracle", file=sys.stderr, flush=True)
-            line["precision_error"] = precision_errors(args, cats[-1][1], lmax, outs[-1], prec)
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cats, lmax, args.cpu_seconds)
+    line.update({"metric": METRIC, "value": value, "unit": UNIT,
+                 "n_gpus": 1, "steps": steps, "warmup": res["warmup_done"], "steps_requested": args.steps,
+                 "warmup_requested": args.warmup, "ms_per_step": round(ms_per_step, 3),
+                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                 "dtype": {"fp64": "f64", "mixed": "f64 recurrence + f32 products",
+                           "fp32": "f32 + f64"}[args.precision], "data": "synthetic",
+                 "config": {"workload": wl["desc"], "lmax": lmax, "points": sum(n for *_, n in dev),
+                            "terms_per_step": terms_per_step, "precision": args.precision,
+                            "points_per_lane": args.points_per_lane or "default",
+                            "l_block": args.l_block or "default"},
+                 "roofline": roofline,
+                 "time_budget_s": args.time_budget})
+    if want_mixed and (res["optional"] or budget.left() > 1.05 * res["step_s"] + 15.0):
+        print("[bench] mixed-precision step on the same catalog", file=sys.stderr, flush=True)
+        line["mixed"] = mixed_record(dev[0], outs[0], lmax, terms_per_step, k_ms)
+    elif want_mixed:
+        line["mixed"] = {"skipped": f"no room in the {args.time_budget:.0f} s budget for one more step"}
+    line["wall_s"] = round(time.monotonic() - START, 1)
     print(json.dumps(line), flush=True)
+
+
+def mixed_record(d, out64, lmax, terms, fp64_kernel_ms):
+    """One MIXED (FP64 recurrence, FP32 products) transform of the same catalog: its rate, kernel
+    time and error per l against the FP64 result of the timed steps."""
+    import numpy as np
+    import torch
+    from paper_2312_12285_amd import ptalm
+    _, t, p, w, n = d
+    out = torch.empty_like(out64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ptalm.alm_from_points(t, p, w, lmax, out=out, options=ptalm.opts(precision=ptalm.MIXED, timing=1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms = ptalm.last_timing_ms()
+    err = per_l_errors(ptalm.as_complex(out).cpu().numpy(), ptalm.as_complex(out64).cpu().numpy(), lmax)
+    return {"value": terms / wall, "unit": UNIT, "steps": 1, "kernel_ms_per_launch": round(k_ms, 3),
+            "dtype": "f64 recurrence + f32 products",
+            "speedup_over_fp64_kernel": round(fp64_kernel_ms / k_ms, 4), "error_vs_fp64": err}
 
 
 if __name__ == "__main__":
