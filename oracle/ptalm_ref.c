@@ -360,7 +360,7 @@ int ptalm_ref_cross_cl(const double *alm1, const double *alm2, int lmax, double 
 int64_t ptalm_ref_alm_size(int lmax) { return lmax < 0 ? 0 : tri_size(lmax); }
 
 /* ---------------------------------------------------------------------------
- * Mode coupling (Sec. 2.1 eq. chat) and the 3j symbols it needs (App. C).
+ * Mode coupling (Sec. 2.1 eq. chat) and the 3j symbols it needs (App. B).
  * ------------------------------------------------------------------------- */
 
 static long double lfact(int k) { return lgammal((long double)k + 1.0L); }

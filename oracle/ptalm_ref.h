@@ -52,7 +52,7 @@ int ptalm_ref_cl_from_alm(const double *alm, int lmax, double *cl);
 /* Cross spectrum C^AB_l = (2l+1)^-1 sum_{m=-l..l} Re(a_lm conj(b_lm)). */
 int ptalm_ref_cross_cl(const double *alm1, const double *alm2, int lmax, double *cl);
 
-/* Wigner 3j symbol (l1 l2 l3; 0 0 0) (App. C), from its closed form for zero
+/* Wigner 3j symbol (l1 l2 l3; 0 0 0) (App. B), from its closed form for zero
  * projections evaluated in long double with log-gamma:
  *   (-1)^(L/2) sqrt[(L-2l1)! (L-2l2)! (L-2l3)! / (L+1)!] (L/2)! / [(L/2-l1)! (L/2-l2)! (L/2-l3)!],
  * L = l1+l2+l3; 0 when L is odd or the triangle condition fails. */

@@ -189,11 +189,11 @@ def cross_cl(alm1, alm2, lmax: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Mode coupling and bandpowers (Sec. 2.1 eq. chat, eq. mode_coupling; App. C)
+# Mode coupling and bandpowers (Sec. 2.1 eq. chat, eq. mode_coupling; App. B)
 # ---------------------------------------------------------------------------
 
 def threej000(l1: int, l2: int, l3: int) -> float:
-    """(l1 l2 l3; 0 0 0), closed form (App. C)."""
+    """(l1 l2 l3; 0 0 0), closed form (App. B)."""
     return float(_load().ptalm_ref_threej000(int(l1), int(l2), int(l3)))
 
 

@@ -1,4 +1,4 @@
-// Mode coupling and bandpowers (Sec. 2.1 eq. chat, eq. mode_coupling, eq. expectation_value; App. C).
+// Mode coupling and bandpowers (Sec. 2.1 eq. chat, eq. mode_coupling, eq. expectation_value; App. B).
 //
 // M[l][l'] = (2l'+1)/(4 pi) sum_lambda (2 lambda + 1) (l l' lambda; 0 0 0)^2 W_lambda.
 //
@@ -16,7 +16,7 @@
 // cores (16x16x4 f64) with operands formed on the fly from three short tables.
 // Every factor is positive, so with W >= 0 the sums carry no cancellation;
 // a(n) comes from a double-double prefix product and is correct to rounding.
-// The paper's own route (its App. C recurrence for the 3j symbols) gives the
+// The paper's own route (its App. B recurrence for the 3j symbols) gives the
 // same numbers; the oracle uses the factorial closed form.
 //
 // Bandpowers: theta_b^l = 1/delta_l on complete bins [lmin + b delta_l, lmin + (b+1) delta_l).

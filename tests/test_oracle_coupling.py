@@ -1,7 +1,7 @@
-"""Pins of the mode-coupling oracle (Sec. 2.1 eq. chat, eq. mode_coupling; App. C).
+"""Pins of the mode-coupling oracle (Sec. 2.1 eq. chat, eq. mode_coupling; App. B).
 
 The oracle's 3j symbols come from the closed form; they are pinned to a
-textbook table, to the paper's own recurrence and terminal case (App. C), to
+textbook table, to the paper's own recurrence and terminal case (App. B), to
 the Gaunt integral of three Legendre polynomials by Gauss-Legendre quadrature
 (scipy, no 3j involved), and to their orthogonality sum.  The coupling matrix
 is pinned to its meaning: M_ll' = (2l+1)^-1 sum_m sum_m' |int w Y_l'm' Y*_lm|^2
@@ -33,7 +33,7 @@ def test_threej_zero_cases(oracle):
 
 
 def test_threej_paper_terminal_and_recurrence(oracle):
-    """App. C: (l l 0; 000) = (-1)^l / sqrt(2l+1), and the ratio recurrence in (l2, l3)."""
+    """App. B: (l l 0; 000) = (-1)^l / sqrt(2l+1), and the ratio recurrence in (l2, l3)."""
     for l in (0, 1, 2, 7, 50, 333, 1000):
         assert abs(oracle.threej000(l, l, 0) - (-1) ** l / math.sqrt(2 * l + 1)) <= 1e-14 / math.sqrt(2 * l + 1)
     rng = np.random.default_rng(3)
