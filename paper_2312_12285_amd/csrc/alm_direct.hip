@@ -252,18 +252,28 @@ __global__ __launch_bounds__(64) void alm_direct_kernel(AlmArgs args) {
     }
 }
 
-// Second pass: a_lm = sigma_lm * sum_{s<S} partial_s[l, m], slices in order.
+// Neumaier's compensated addition: sum + c carries the exact running total to
+// within one rounding of the final result, whatever the order of magnitudes.
+__device__ inline void neumaier_add(double &sum, double &c, double v) {
+    const double t = sum + v;
+    c += (fabs(sum) >= fabs(v)) ? (sum - t) + v : (v - t) + sum;
+    sum = t;
+}
+
+// Second pass: a_lm = sigma_lm * sum_{s<S} partial_s[l, m], slices in order, in
+// FP64 with compensation (the cross-slice sum is the last reduction of every form,
+// so the reduced-precision forms end in a compensated FP64 reduction too).
 __global__ void reduce_partials_kernel(const double *__restrict__ partial, int n_slices,
                                        const double *__restrict__ sigma, int64_t T, double *__restrict__ alm) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < T; k += (int64_t)gridDim.x * blockDim.x) {
-        double re = 0.0, im = 0.0;
+        double re = 0.0, im = 0.0, cre = 0.0, cim = 0.0;
         for (int s = 0; s < n_slices; ++s) {
             const double2 v = reinterpret_cast<const double2 *>(partial + (int64_t)s * 2 * T)[k];
-            re += v.x;
-            im += v.y;
+            neumaier_add(re, cre, v.x);
+            neumaier_add(im, cim, v.y);
         }
         const double sg = sigma[k];
-        reinterpret_cast<double2 *>(alm)[k] = make_double2(sg * re, sg * im);
+        reinterpret_cast<double2 *>(alm)[k] = make_double2(sg * (re + cre), sg * (im + cim));
     }
 }
 
