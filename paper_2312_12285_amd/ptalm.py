@@ -127,6 +127,17 @@ def _dev_f64(t, name):
     return t
 
 
+def _need(t, count: int, name: str):
+    """The C ABI takes raw pointers, so buffer sizes are checked here, before any launch."""
+    if t.numel() < count:
+        raise ValueError(f"{name} holds {t.numel()} elements, the call needs {count}")
+
+
+def _lmax_ok(lmax: int):
+    if not (isinstance(lmax, int) and 0 <= lmax <= LMAX_MAX):
+        raise ValueError(f"lmax must be an int in [0, {LMAX_MAX}]")
+
+
 def alm_size(lmax: int) -> int:
     return int(_alm_size(lmax))
 
@@ -192,8 +203,12 @@ def workspace_bytes(n: int, lmax: int, options: Opts | None = None) -> int:
 def cl_from_alm(alm, lmax: int, out=None, stream=None):
     """C_l = (2l+1)^-1 sum_{m=-l..l} |a_lm|^2 (float64 [lmax+1])."""
     _dev_f64(alm, "alm")
+    _lmax_ok(lmax)
+    _need(alm, 2 * alm_size(lmax), "alm")
     if out is None:
         out = torch.empty(lmax + 1, dtype=torch.float64, device=alm.device)
+    _dev_f64(out, "out")
+    _need(out, lmax + 1, "out")
     _check(_cl(_ptr(alm), lmax, _ptr(out), _stream(stream)))
     return out
 
@@ -201,8 +216,12 @@ def cl_from_alm(alm, lmax: int, out=None, stream=None):
 def cross_cl(alm1, alm2, lmax: int, out=None, stream=None):
     """C^AB_l = (2l+1)^-1 sum_{m=-l..l} Re(a_lm conj(b_lm)) (float64 [lmax+1])."""
     _dev_f64(alm1, "alm1"); _dev_f64(alm2, "alm2")
+    _lmax_ok(lmax)
+    _need(alm1, 2 * alm_size(lmax), "alm1"); _need(alm2, 2 * alm_size(lmax), "alm2")
     if out is None:
         out = torch.empty(lmax + 1, dtype=torch.float64, device=alm1.device)
+    _dev_f64(out, "out")
+    _need(out, lmax + 1, "out")
     _check(_cross(_ptr(alm1), _ptr(alm2), lmax, _ptr(out), _stream(stream)))
     return out
 
@@ -210,6 +229,8 @@ def cross_cl(alm1, alm2, lmax: int, out=None, stream=None):
 def alm_axpy(alpha: float, x, y, lmax: int, stream=None):
     """y <- y + alpha x (in place); returns y."""
     _dev_f64(x, "x"); _dev_f64(y, "y")
+    _lmax_ok(lmax)
+    _need(x, 2 * alm_size(lmax), "x"); _need(y, 2 * alm_size(lmax), "y")
     _check(_axpy(float(alpha), _ptr(x), _ptr(y), lmax, _stream(stream)))
     return y
 
@@ -218,6 +239,8 @@ def fkp_fields(alm_data, alm_randoms, lmax: int, stream=None):
     """(delta, window, alpha): alpha = a00(d)/a00(r) on the device, delta = a(d) - alpha a(r),
     window = alpha a(r)."""
     _dev_f64(alm_data, "alm_data"); _dev_f64(alm_randoms, "alm_randoms")
+    _lmax_ok(lmax)
+    _need(alm_data, 2 * alm_size(lmax), "alm_data"); _need(alm_randoms, 2 * alm_size(lmax), "alm_randoms")
     delta = torch.empty_like(alm_data)
     window = torch.empty_like(alm_data)
     alpha = torch.empty(1, dtype=torch.float64, device=alm_data.device)
@@ -233,8 +256,13 @@ def prepare(lmax: int):
 def window_shot_noise(w, alpha=None, out=None, stream=None):
     """alpha^2 sum_i w_i^2 / (4 pi) (device scalar tensor); alpha a 1-element device tensor or None."""
     _dev_f64(w, "w")
+    if alpha is not None:
+        _dev_f64(alpha, "alpha")
+        _need(alpha, 1, "alpha")
     if out is None:
         out = torch.empty(1, dtype=torch.float64, device=w.device)
+    _dev_f64(out, "out")
+    _need(out, 1, "out")
     _check(_shot(_ptr(w), w.numel(), None if alpha is None else _ptr(alpha), _ptr(out), _stream(stream)))
     return out
 
@@ -243,8 +271,14 @@ def coupling_matrix(Wl, lmax: int, shot=None, out=None, stream=None):
     """Mode-coupling matrix M[l, l'] (eq. chat) from the window spectrum Wl[0..lmax_w]; float64
     [(lmax+1), (lmax+1)].  shot: optional 1-element device tensor subtracted from W first."""
     _dev_f64(Wl, "Wl")
+    _lmax_ok(lmax)
+    if shot is not None:
+        _dev_f64(shot, "shot")
+        _need(shot, 1, "shot")
     if out is None:
         out = torch.empty((lmax + 1, lmax + 1), dtype=torch.float64, device=Wl.device)
+    _dev_f64(out, "out")
+    _need(out, (lmax + 1) ** 2, "out")
     _check(_coupling(_ptr(Wl), Wl.numel() - 1, None if shot is None else _ptr(shot), lmax, _ptr(out),
                      _stream(stream)))
     return out
@@ -257,6 +291,8 @@ def bandpower_count(lmax: int, lmin: int, delta_l: int) -> int:
 def bandpowers(cl_hat, M, lmax: int, delta_l: int, lmin: int = 0, mode: int = 0, Wl=None, stream=None):
     """(cb, window): mode 0 mode-decoupled (eq. mode_coupling), 1 normalised."""
     _dev_f64(cl_hat, "cl_hat"); _dev_f64(M, "M")
+    _lmax_ok(lmax)
+    _need(cl_hat, lmax + 1, "cl_hat"); _need(M, (lmax + 1) ** 2, "M")
     nb = bandpower_count(lmax, lmin, delta_l)
     cb = torch.empty(max(nb, 1), dtype=torch.float64, device=M.device)
     window = torch.empty((max(nb, 1), lmax + 1), dtype=torch.float64, device=M.device)
