@@ -40,3 +40,20 @@ def oracle():
     from oracle import ref
     ref._load()
     return ref
+
+
+# Measured figures that tests state (error curves and the like): collected during the run and
+# printed in the terminal summary, so they reach the log whatever the verbosity.
+_MEASURED = []
+
+
+@pytest.fixture(scope="session")
+def measured():
+    return _MEASURED
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    if _MEASURED:
+        terminalreporter.section("measured")
+        for line in _MEASURED:
+            terminalreporter.write_line(line)
