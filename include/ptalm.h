@@ -153,7 +153,7 @@ int ptalm_fkp_fields(const double *alm_data, const double *alm_randoms, int lmax
 
 /* ------------------------------------------------------------------------
  * Mode coupling and bandpowers (Sec. 2.1 eq. chat, eq. mode_coupling,
- * eq. expectation_value; 3j symbols of App. C).  Device pointers, async on
+ * eq. expectation_value; 3j symbols of App. B).  Device pointers, async on
  * `stream`.
  * ------------------------------------------------------------------------ */
 
@@ -173,7 +173,7 @@ int ptalm_window_shot_noise(const double *w, int64_t n, const double *alpha, dou
  * FP64.  With J = (l + l' + lambda)/2 and a(n) = binom(2n, n)/4^n the 3j square
  * is a(J-l) a(J-l') a(J-lambda) / ((2J+1) a(J)); the matrix is computed as a
  * triangular matrix product on the matrix cores from tables of a(n) (the same
- * values the App. C recurrence gives).  Allocates stream-ordered scratch.
+ * values the App. B recurrence gives).  Allocates stream-ordered scratch.
  * PTALM_EINVAL on bad sizes or NULL pointers. */
 int ptalm_coupling_matrix(const double *Wl, int lmax_w, const double *shot, int lmax, double *M, void *stream);
 
@@ -217,17 +217,33 @@ int ptalm_bandpowers(const double *cl_hat, const double *M, const double *Wl, in
  * a_lm = sum_j [v_j0 y(x_j) + v_j1 dx_j y'(x_j) + v_j2 y(x_{j+1}) + v_j3 dx_j y'(x_{j+1})]
  * with y' from the derivative relation of App. A.1.  Approximate: the error
  * falls like (l h)^4 with the node spacing h in theta.  FP64 throughout.
- * Allocates stream-ordered scratch (about 64 B per point, plus
- * (lmax+1) x n_nodes x 112 B, plus about 270 B per (l, m)) and synchronizes
- * `stream` once (to size the polar part).  Points inside one interval are
- * summed in the order a scatter with atomic counters placed them, so repeated
- * calls can differ in the last bits.  opts: NULL, or opts->timing != 0 to
- * record HIP events around the binning kernel (the dominant one) on `stream`,
- * read with ptalm_last_timing(); the other fields are not used.
- * PTALM_EINVAL on bad sizes or pointers, or n > PTALM_SPLINE_N_MAX. */
+ * The points are put in interval order by a stable counting sort (inside an
+ * interval they keep their input order), so repeated calls give the same bits.
+ * Scratch: ptalm_spline_workspace_bytes(n, lmax, n_nodes) bytes (about 88 B per
+ * point, plus (lmax+1) x n_nodes x 112 B, plus about 270 B per (l, m)); with
+ * workspace != NULL (device, 256-byte aligned, ws_bytes at least that) the call
+ * uses it and allocates nothing, else it allocates stream-ordered scratch.  The
+ * call never synchronizes: the number of polar points stays on the device.  It
+ * can be captured into a HIP graph when given a workspace after
+ * ptalm_prepare_spline_call(n, lmax, n_nodes) (else PTALM_EINVAL without a
+ * workspace, PTALM_EBUSY when not prepared).  opts: NULL, or opts->timing != 0
+ * to record HIP events around the binning kernel (the dominant one) on
+ * `stream`, read with ptalm_last_timing() (not under capture); the other fields
+ * are not used.  PTALM_EINVAL on bad sizes or pointers, a small or misaligned
+ * workspace, or n > PTALM_SPLINE_N_MAX. */
 int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
                                  int n_nodes, double theta_cut, double *alm, const ptalm_opts *opts,
-                                 void *stream);
+                                 void *workspace, size_t ws_bytes, void *stream);
+
+/* Scratch bytes of ptalm_alm_from_points_spline for these sizes (0 on bad
+ * arguments).  Host only. */
+size_t ptalm_spline_workspace_bytes(int64_t n, int lmax, int n_nodes);
+
+/* Builds, on the current device, the tables a later
+ * ptalm_alm_from_points_spline(n, lmax, n_nodes, ...) call needs (direct-sum
+ * coefficient tables for the polar caps, the m-range tables of the node sum
+ * and of the polar sum), so that the call can be captured.  Host only. */
+int ptalm_prepare_spline_call(int64_t n, int lmax, int n_nodes);
 
 /*
  * Spin-weighted transform for shear (spin +-2 harmonics in place of Y_lm, the

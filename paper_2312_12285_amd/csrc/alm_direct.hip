@@ -70,11 +70,24 @@ __global__ __launch_bounds__(64) void alm_direct_kernel(AlmArgs args) {
     const int m_b = __builtin_amdgcn_readfirstlane(args.range_m[r + 1]);
     const const_ptr<RecT> coef =
         (const_ptr<RecT>)(sizeof(RecT) == 8 ? (const void *)args.coef : (const void *)args.coef32);
-    const int64_t g_a = (int64_t)s * args.groups / args.n_slices;
-    const int64_t g_b = (int64_t)(s + 1) * args.groups / args.n_slices;
+    // the point count, from the device when the caller's count lives there
+    const int64_t n = args.n_dev ? *args.n_dev : args.n;
+    const int64_t groups = args.n_dev ? (n + 64 * KP - 1) / (64 * KP) : args.groups;
+    const int64_t g_a = (int64_t)s * groups / args.n_slices;
+    const int64_t g_b = (int64_t)(s + 1) * groups / args.n_slices;
     double *part = args.partial + (int64_t)s * 2 * tri_size(lmax);
     const int v = lane / P;  // reduced value this lane finishes (owner when h == 0)
     const int h = lane % P;
+
+    if (g_a >= g_b) {
+        // a slice without points (only when the count comes from the device and
+        // is below the planned slice count): its partial columns are zero
+        for (int m = m_a; m < m_b; ++m) {
+            double *pm = part + 2 * column_start(lmax, m);
+            for (int k = lane; k < 2 * (lmax - m + 1); k += 64) pm[k] = 0.0;
+        }
+        return;
+    }
 
     for (int64_t g = g_a; g < g_b; ++g) {
         const bool first = (g == g_a);
@@ -85,7 +98,7 @@ __global__ __launch_bounds__(64) void alm_direct_kernel(AlmArgs args) {
         for (int t = 0; t < KP; ++t) {
             const int64_t i = g * (64 * KP) + t * 64 + lane;
             double th = 1.5707963267948966, ph = 0.0, ww = 0.0;
-            if (i < args.n) {
+            if (i < n) {
                 th = args.theta[i];
                 ph = args.phi[i];
                 ww = args.w[i];

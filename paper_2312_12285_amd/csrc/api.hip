@@ -525,80 +525,172 @@ struct AsyncAllocs {
 
 }  // namespace
 
-int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
-                                 int n_nodes, double theta_cut, double *alm, const ptalm_opts *opts, void *stream_) {
-    g_error.clear();
+}  // extern "C"
+
+namespace {
+
+// Scratch of the interpolated transform: one buffer cut into 256-byte aligned
+// parts (sizes from the upper bound n on both the spline and the polar counts,
+// so nothing depends on the device-side split and nothing is read back).
+struct SplineScratch {
+    size_t xn, thn, H, counts, offsets, npolar, q, pth, pph, pw, v, wn, state, ppart, ptmp, total;
+    ptalm::SplinePlan plan;
+    Resolved polar;   // plan of the exact sum over the polar points (for n of them at most)
+};
+
+int spline_scratch(int64_t n, int lmax, int n_nodes, SplineScratch *s) {
+    s->plan = ptalm::spline_plan(n, lmax, n_nodes);
+    int rc = resolve(std::max<int64_t>(n, 1), lmax, nullptr, &s->polar);
+    if (rc) return rc;
+    const int64_t T = ptalm::tri_size(lmax);
+    const int nb = n_nodes;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes < 256 ? 256 : bytes);
+        return at;
+    };
+    s->xn = take(sizeof(double) * n_nodes);
+    s->thn = take(sizeof(double) * n_nodes);
+    s->H = take(sizeof(unsigned) * (size_t)s->plan.sort_chunks * nb);
+    s->counts = take(sizeof(unsigned) * nb);
+    s->offsets = take(sizeof(int64_t) * (nb + 1));
+    s->npolar = take(sizeof(int64_t));
+    s->q = take(sizeof(double) * 8 * (size_t)n);
+    s->pth = take(sizeof(double) * (size_t)n);
+    s->pph = take(sizeof(double) * (size_t)n);
+    s->pw = take(sizeof(double) * (size_t)n);
+    s->v = take(sizeof(double) * s->plan.v_doubles);
+    s->wn = take(sizeof(double) * s->plan.wn_doubles);
+    s->state = take(sizeof(double) * s->plan.state_doubles);
+    s->ppart = take(partial_bytes(s->polar, lmax));
+    s->ptmp = take(sizeof(double) * 2 * (size_t)T);
+    s->total = off;
+    return PTALM_OK;
+}
+
+int spline_args_ok(int64_t n, int lmax, int n_nodes) {
     if (n < 0) return fail(PTALM_EINVAL, "n < 0");
     if (n > PTALM_SPLINE_N_MAX) return fail(PTALM_EINVAL, "n above PTALM_SPLINE_N_MAX (32-bit per-interval counters)");
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (n_nodes < 2 || n_nodes > PTALM_SPLINE_NODES_MAX) return fail(PTALM_EINVAL, "n_nodes out of range");
+    return PTALM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ptalm_spline_workspace_bytes(int64_t n, int lmax, int n_nodes) {
+    if (n < 0 || n > PTALM_SPLINE_N_MAX || !lmax_ok(lmax) || n_nodes < 2 || n_nodes > PTALM_SPLINE_NODES_MAX) return 0;
+    SplineScratch s;
+    if (spline_scratch(n, lmax, n_nodes, &s)) return 0;
+    return s.total;
+}
+
+int ptalm_prepare_spline_call(int64_t n, int lmax, int n_nodes) {
+    g_error.clear();
+    int rc = spline_args_ok(n, lmax, n_nodes);
+    if (rc) return rc;
+    SplineScratch s;
+    if ((rc = spline_scratch(n, lmax, n_nodes, &s))) return rc;
+    const ptalm::Tables *tab;
+    const int *ranges;
+    if ((rc = get_tables(lmax, &tab))) return rc;
+    if ((rc = get_ranges(lmax, s.plan.ns_ranges, &ranges))) return rc;
+    return get_ranges(lmax, s.polar.R, &ranges);
+}
+
+int ptalm_alm_from_points_spline(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
+                                 int n_nodes, double theta_cut, double *alm, const ptalm_opts *opts, void *workspace,
+                                 size_t ws_bytes, void *stream_) {
+    g_error.clear();
+    int rc = spline_args_ok(n, lmax, n_nodes);
+    if (rc) return rc;
     if (alm == nullptr || (n > 0 && (theta == nullptr || phi == nullptr || w == nullptr)))
         return fail(PTALM_EINVAL, "NULL pointer");
-    if (n_nodes < 2 || n_nodes > PTALM_SPLINE_NODES_MAX) return fail(PTALM_EINVAL, "n_nodes out of range");
     const double kPi = 3.141592653589793;
     if (!(theta_cut > 0.0 && theta_cut < 0.5 * kPi)) return fail(PTALM_EINVAL, "theta_cut must be in (0, pi/2)");
+    SplineScratch sc;
+    if ((rc = spline_scratch(n, lmax, n_nodes, &sc))) return rc;
+    if (workspace != nullptr && ws_bytes < sc.total) return fail(PTALM_EINVAL, "workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(PTALM_EINVAL, "workspace not 256-byte aligned");
     hipStream_t stream = (hipStream_t)stream_;
-    const double h = (kPi - 2.0 * theta_cut) / (n_nodes - 1);
-    const int64_t T = ptalm::tri_size(lmax);
-    AsyncAllocs mem(stream);
-    double *xn, *thn;
-    unsigned *counts, *cursors;
-    int64_t *offsets;
-    hipError_t e;
-    if ((e = mem.get((void **)&xn, sizeof(double) * n_nodes)) != hipSuccess ||
-        (e = mem.get((void **)&thn, sizeof(double) * n_nodes)) != hipSuccess ||
-        (e = mem.get((void **)&counts, sizeof(unsigned) * n_nodes)) != hipSuccess ||
-        (e = mem.get((void **)&cursors, sizeof(unsigned) * n_nodes)) != hipSuccess ||
-        (e = mem.get((void **)&offsets, sizeof(int64_t) * (n_nodes + 1))) != hipSuccess)
-        return fail_hip(e, "hipMallocAsync");
-    if ((e = ptalm::launch_spline_count(theta, n, theta_cut, h, n_nodes, xn, thn, counts, stream)) != hipSuccess)
-        return fail_hip(e, "spline count kernels");
-    // the polar count sizes the arrays below: one synchronisation
-    unsigned n_polar_u = 0;
-    if ((e = hipMemcpyAsync(&n_polar_u, counts + (n_nodes - 1), sizeof(unsigned), hipMemcpyDeviceToHost, stream)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(stream)) != hipSuccess)
-        return fail_hip(e, "reading the polar count");
-    const int64_t n_polar = n_polar_u, n_spline = n - n_polar;
-    double *q, *pth, *pph, *pw;
-    if ((e = mem.get((void **)&q, sizeof(double) * 8 * (size_t)n_spline)) != hipSuccess ||
-        (e = mem.get((void **)&pth, sizeof(double) * (size_t)n_polar)) != hipSuccess ||
-        (e = mem.get((void **)&pph, sizeof(double) * (size_t)n_polar)) != hipSuccess ||
-        (e = mem.get((void **)&pw, sizeof(double) * (size_t)n_polar)) != hipSuccess)
-        return fail_hip(e, "hipMallocAsync");
-    if ((e = ptalm::launch_spline_scatter(theta, phi, w, n, theta_cut, h, n_nodes, xn, counts, offsets, cursors, q,
-                                          n_spline, pth, pph, pw, stream)) != hipSuccess)
-        return fail_hip(e, "spline scatter kernels");
-    const ptalm::SplinePlan plan = ptalm::spline_plan(n, lmax, n_nodes);
-    double *v, *wn, *state;
-    if ((e = mem.get((void **)&v, sizeof(double) * plan.v_doubles)) != hipSuccess ||
-        (e = mem.get((void **)&wn, sizeof(double) * plan.wn_doubles)) != hipSuccess ||
-        (e = mem.get((void **)&state, sizeof(double) * plan.state_doubles)) != hipSuccess)
-        return fail_hip(e, "hipMallocAsync");
-    const int *ranges;
-    int rc_r = get_ranges(lmax, plan.ns_ranges, &ranges);
-    if (rc_r != PTALM_OK) return rc_r;
     const bool timed = opts != nullptr && opts->timing != 0;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cap);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamIsCapturing");
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing && timed) return fail(PTALM_EINVAL, "timing is not available under stream capture");
+    if (capturing && workspace == nullptr) return fail(PTALM_EINVAL, "stream capture needs a caller workspace");
+    const ptalm::Tables *tab;
+    const int *ns_ranges, *polar_ranges;
+    if ((rc = get_tables(lmax, &tab, !capturing)) || (rc = get_ranges(lmax, sc.plan.ns_ranges, &ns_ranges, !capturing)) ||
+        (rc = get_ranges(lmax, sc.polar.R, &polar_ranges, !capturing)))
+        return rc;
     if (timed) {
         g_timing.valid = false;
         if (!g_timing.start && (e = hipEventCreate(&g_timing.start)) != hipSuccess) return fail_hip(e, "hipEventCreate");
         if (!g_timing.stop && (e = hipEventCreate(&g_timing.stop)) != hipSuccess) return fail_hip(e, "hipEventCreate");
     }
-    if ((e = ptalm::launch_spline_transform(plan, q, n_spline, offsets, xn, thn, n_nodes, lmax, (double2 *)v,
-                                            (double2 *)wn, state, ranges, alm, stream,
-                                            timed ? g_timing.start : nullptr, timed ? g_timing.stop : nullptr)) !=
-        hipSuccess)
-        return fail_hip(e, "spline transform kernels");
-    if (timed) g_timing.valid = true;
-    if (n_polar > 0) {   // the polar caps by the exact sum, added to the interpolated part
-        double *tmp;
-        if ((e = mem.get((void **)&tmp, sizeof(double) * 2 * (size_t)T)) != hipSuccess)
-            return fail_hip(e, "hipMallocAsync");
-        const int rc = ptalm_alm_from_points_ex(pth, pph, pw, n_polar, lmax, tmp, nullptr, nullptr, 0, stream);
-        if (rc != PTALM_OK) return rc;
-        if ((e = ptalm::launch_axpy(1.0, tmp, alm, 2 * T, stream)) != hipSuccess) return fail_hip(e, "axpy");
+    char *base = (char *)workspace;
+    bool own = false;
+    if (base == nullptr) {
+        if ((e = hipMallocAsync((void **)&base, sc.total, stream)) != hipSuccess)
+            return fail_hip(e, "hipMallocAsync(scratch)");
+        own = true;
     }
-    if ((e = mem.release()) != hipSuccess) return fail_hip(e, "hipFreeAsync");
-    return PTALM_OK;
+    const double h = (kPi - 2.0 * theta_cut) / (n_nodes - 1);
+    const int64_t T = ptalm::tri_size(lmax);
+    double *xn = (double *)(base + sc.xn), *thn = (double *)(base + sc.thn);
+    int64_t *offsets = (int64_t *)(base + sc.offsets), *n_polar = (int64_t *)(base + sc.npolar);
+    double *q = (double *)(base + sc.q);
+    double *pth = (double *)(base + sc.pth), *pph = (double *)(base + sc.pph), *pw = (double *)(base + sc.pw);
+    double *ptmp = (double *)(base + sc.ptmp);
+    // points in interval order (stable), polar points apart; the polar count stays on the device
+    e = ptalm::launch_spline_sort(theta, phi, w, n, theta_cut, h, n_nodes, sc.plan, xn, thn, (unsigned *)(base + sc.H),
+                                  (unsigned *)(base + sc.counts), offsets, n_polar, q, pth, pph, pw, stream);
+    if (e != hipSuccess) rc = fail_hip(e, "spline sort kernels");
+    if (rc == PTALM_OK &&
+        (e = ptalm::launch_spline_transform(sc.plan, q, n, offsets, xn, thn, n_nodes, lmax, (double2 *)(base + sc.v),
+                                            (double2 *)(base + sc.wn), (double *)(base + sc.state), ns_ranges, alm,
+                                            stream, timed ? g_timing.start : nullptr,
+                                            timed ? g_timing.stop : nullptr)) != hipSuccess)
+        rc = fail_hip(e, "spline transform kernels");
+    if (rc == PTALM_OK && timed) g_timing.valid = true;
+    if (rc == PTALM_OK && n > 0) {
+        // the polar caps by the exact sum over the device-side count of polar points
+        // (planned for n of them), added to the interpolated part
+        ptalm::AlmArgs a;
+        a.theta = pth;
+        a.phi = pph;
+        a.w = pw;
+        a.n = n;
+        a.lmax = lmax;
+        a.n_ranges = sc.polar.R;
+        a.n_slices = sc.polar.S;
+        a.groups = sc.polar.groups;
+        a.range_m = polar_ranges;
+        a.coef = tab->coef;
+        a.coef32 = tab->coef32;
+        a.partial = (double *)(base + sc.ppart);
+        a.w_stride = n;
+        a.n_weights = 1;
+        a.n_dev = n_polar;
+        bool supported = true;
+        e = ptalm::launch_alm_fp64(a, sc.polar.kp, sc.polar.lb, sc.polar.mode, stream, &supported);
+        if (!supported) rc = fail(PTALM_ENOTSUP, "kernel variant not compiled");
+        else if (e != hipSuccess) rc = fail_hip(e, "polar transform launch");
+        else if ((e = ptalm::launch_reduce_partials(a.partial, sc.polar.S, tab->sigma, lmax, ptmp, stream)) != hipSuccess)
+            rc = fail_hip(e, "polar reduce launch");
+        else if ((e = ptalm::launch_axpy(1.0, ptmp, alm, 2 * T, stream)) != hipSuccess)
+            rc = fail_hip(e, "axpy");
+    }
+    if (own) {
+        e = hipFreeAsync(base, stream);
+        if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync(scratch)");
+    }
+    return rc;
 }
 
 namespace {

@@ -66,6 +66,9 @@ struct AlmArgs {
     double *partial;          // device, n_slices * 2T doubles
     int64_t w_stride;         // multi-weight: distance between weight rows
     int n_weights;
+    // when set, the number of points is read here on the device (n and groups
+    // above are then upper bounds used only by the plan)
+    const int64_t *n_dev = nullptr;
 };
 
 // Arguments of the multi-weight MFMA kernels.
@@ -133,6 +136,8 @@ hipError_t launch_shot_noise(const double *w, int64_t n, const double *alpha, do
 // interpolated transform (spline.hip)
 struct SplinePlan {
     int n_int = 0, n_pass = 0;
+    int sort_chunks = 1;                // stable sort: chunks of the input (one wavefront each)
+    int64_t sort_chunk = 1;             // points per chunk
     int ns_slices = 0, ns_ranges = 0;   // node sum: node slices x order ranges
     int64_t ns_groups = 0;              // node groups of 64 KP
     size_t v_doubles = 0, wn_doubles = 0, state_doubles = 0;
@@ -151,12 +156,10 @@ struct NodeSumArgs {
     double *partial;          // n_slices * 4T doubles
 };
 SplinePlan spline_plan(int64_t n, int lmax, int n_nodes);
-hipError_t launch_spline_count(const double *theta, int64_t n, double theta_cut, double h, int n_nodes, double *xn,
-                               double *thn, unsigned *counts, hipStream_t stream);
-hipError_t launch_spline_scatter(const double *theta, const double *phi, const double *w, int64_t n, double theta_cut,
-                                 double h, int n_nodes, const double *xn, const unsigned *counts, int64_t *offsets,
-                                 unsigned *cursors, double *q, int64_t n_spline, double *pth, double *pph, double *pw,
-                                 hipStream_t stream);
+hipError_t launch_spline_sort(const double *theta, const double *phi, const double *w, int64_t n, double theta_cut,
+                              double h, int n_nodes, const SplinePlan &p, double *xn, double *thn, unsigned *H,
+                              unsigned *counts, int64_t *offsets, int64_t *n_polar, double *q, double *pth, double *pph,
+                              double *pw, hipStream_t stream);
 hipError_t launch_spline_transform(const SplinePlan &p, const double *q, int64_t n_spline, const int64_t *offsets,
                                    const double *xn, const double *thn, int n_nodes, int lmax, double2 *v,
                                    double2 *wn, double *state, const int *ranges, double *alm, hipStream_t stream,

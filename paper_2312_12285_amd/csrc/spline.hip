@@ -44,11 +44,6 @@ __device__ inline int interval_of(double th, double theta_cut, double h, int n_i
     return j < n_int - 1 ? j : n_int - 1;
 }
 
-__global__ void zero_u32_kernel(unsigned *p, int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0u;
-}
-
 __global__ void nodes_kernel(double theta_cut, double h, int n_nodes, double *__restrict__ xn,
                              double *__restrict__ thn) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,41 +53,143 @@ __global__ void nodes_kernel(double theta_cut, double h, int n_nodes, double *__
     xn[j] = cos(th);
 }
 
-__global__ void count_kernel(const double *__restrict__ theta, int64_t n, double theta_cut, double h, int n_int,
-                             unsigned *__restrict__ counts) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&counts[interval_of(theta[i], theta_cut, h, n_int)], 1u);
+// Stable counting sort of the points by interval (polar points in the last
+// bucket), so the order of the points inside an interval is their input order
+// and the binning sums are reproducible bit for bit.  The points are cut into
+// fixed chunks, one wavefront each:
+//   chunk_hist_kernel   H[c][b] = points of chunk c in bucket b (LDS histogram);
+//   bucket_total_kernel counts[b] = sum_c H[c][b];  scan_kernel: offsets;
+//   bucket_start_kernel H[c][b] <- offsets[b] + sum_{c' < c} H[c'][b], the place
+//                       of the first point of chunk c in bucket b;
+//   stable_scatter_kernel each wavefront walks its chunk in input order, 64
+//                       points per round; lanes whose points share a bucket are
+//                       ranked by lane index (one ballot per distinct bucket), so
+//                       a point's place is its chunk's start in its bucket plus
+//                       the points of that bucket before it in the chunk.
+// Buckets are handled in windows of kHistMax (one LDS array per wavefront), one
+// pass over the chunk per window.
+constexpr int kHistMax = 16384;      // buckets per LDS window (64 KB)
+constexpr int kSortChunksMax = 1024;
+constexpr int64_t kSortChunkMin = 4096;
+
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// The same counts through a per-workgroup histogram in LDS (nb <= kHistMax
-// buckets): workgroup b takes the contiguous chunk [b chunk, (b+1) chunk) of the
-// points, counts it with LDS atomics and adds each nonzero bucket to the global
-// count once, so contention on the global counters drops by the chunk's
-// points per bucket.
-constexpr int kHistMax = 16384;      // buckets held in LDS (64 KB)
-constexpr int kHistThreads = 1024;
-constexpr int kHistBlocks = 512;
-
-__global__ __launch_bounds__(kHistThreads) void count_lds_kernel(const double *__restrict__ theta, int64_t n,
-                                                                double theta_cut, double h, int n_int, int64_t chunk,
-                                                                unsigned *__restrict__ counts) {
-    extern __shared__ unsigned hist[];
+__global__ __launch_bounds__(64) void chunk_hist_kernel(const double *__restrict__ theta, int64_t n, double theta_cut,
+                                                        double h, int n_int, int64_t chunk,
+                                                        unsigned *__restrict__ H) {
+    __shared__ unsigned hist[kHistMax];
     const int nb = n_int + 1;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
-    __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t c = blockIdx.x;
+    const int64_t lo = c * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-        atomicAdd(&hist[interval_of(theta[i], theta_cut, h, n_int)], 1u);
-    __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+    for (int w0 = 0; w0 < nb; w0 += kHistMax) {
+        const int wn = nb - w0 < kHistMax ? nb - w0 : kHistMax;
+        for (int b = threadIdx.x; b < wn; b += 64) hist[b] = 0u;
+        wave_sync_lds();
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 64) {
+            const int b = interval_of(theta[i], theta_cut, h, n_int) - w0;
+            if (b >= 0 && b < wn) atomicAdd(&hist[b], 1u);   // a count: the order does not matter
+        }
+        wave_sync_lds();
+        for (int b = threadIdx.x; b < wn; b += 64) H[c * nb + w0 + b] = hist[b];
+        wave_sync_lds();
+    }
 }
 
-// offsets[b] = sum_{b' < b} counts[b'] for b <= nb (nb buckets), one workgroup;
-// cursors reset to 0
+__global__ void bucket_total_kernel(const unsigned *__restrict__ H, int n_chunks, int nb,
+                                    unsigned *__restrict__ counts) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    unsigned s = 0u;
+    for (int c = 0; c < n_chunks; ++c) s += H[(int64_t)c * nb + b];
+    counts[b] = s;
+}
+
+// H[c][b] <- offsets[b] + sum_{c' < c} H[c'][b]; the polar count goes to *n_polar
+__global__ void bucket_start_kernel(unsigned *__restrict__ H, int n_chunks, int nb,
+                                    const int64_t *__restrict__ offsets, int64_t *__restrict__ n_polar) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    unsigned run = (unsigned)offsets[b];
+    for (int c = 0; c < n_chunks; ++c) {
+        const unsigned t = H[(int64_t)c * nb + b];
+        H[(int64_t)c * nb + b] = run;
+        run += t;
+    }
+    if (b == nb - 1) *n_polar = offsets[nb] - offsets[nb - 1];
+}
+
+// Points of the spline region in interval order, one 64-byte record each:
+// (w c_0(t), w c_1(t), w c_2(t), w c_3(t), phi / (2 pi), cos phi, sin phi, 0);
+// polar points (bucket n_int) to their own arrays, in input order as well.
+__global__ __launch_bounds__(64) void stable_scatter_kernel(
+    const double *__restrict__ theta, const double *__restrict__ phi, const double *__restrict__ w, int64_t n,
+    double theta_cut, double h, int n_int, int64_t chunk, const double *__restrict__ xn,
+    const int64_t *__restrict__ offsets, const unsigned *__restrict__ start, double *__restrict__ q,
+    double *__restrict__ pth, double *__restrict__ pph, double *__restrict__ pw) {
+    __shared__ unsigned cur[kHistMax];
+    const int nb = n_int + 1;
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int64_t lo = c * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes with a lower index
+    for (int w0 = 0; w0 < nb; w0 += kHistMax) {
+        const int wn = nb - w0 < kHistMax ? nb - w0 : kHistMax;
+        for (int b = lane; b < wn; b += 64) cur[b] = start[c * nb + w0 + b];
+        wave_sync_lds();
+        for (int64_t base = lo; base < hi; base += 64) {
+            const int64_t i = base + lane;
+            double th = 0.0;
+            int j = -1;
+            if (i < hi) {
+                th = theta[i];
+                j = interval_of(th, theta_cut, h, n_int);
+            }
+            const bool act = j >= w0 && j < w0 + wn;
+            uint64_t todo = __ballot(act);
+            unsigned pos = 0u;
+            while (todo) {
+                const int leader = __builtin_ctzll(todo);
+                const int jj = __builtin_amdgcn_readlane(j, leader);
+                const bool mine = act && j == jj;
+                const uint64_t same = __ballot(mine);
+                const unsigned b0 = cur[jj - w0];
+                if (mine) pos = b0 + (unsigned)__popcll(same & below);
+                if (lane == leader) cur[jj - w0] = b0 + (unsigned)__popcll(same);
+                todo &= ~same;
+            }
+            if (!act) continue;
+            const double ph = phi[i], wi = w[i];
+            if (j == n_int) {
+                const int64_t p = (int64_t)pos - offsets[n_int];
+                pth[p] = th;
+                pph[p] = ph;
+                pw[p] = wi;
+                continue;
+            }
+            const double x = cos(th);
+            const double t = (x - xn[j]) / (xn[j + 1] - xn[j]);
+            const double u = 1.0 - t;
+            double sp, cp;
+            sincos(ph, &sp, &cp);
+            double2 *dst = (double2 *)(q + (int64_t)pos * kPointDoubles);
+            dst[0] = make_double2(wi * ((2.0 * t + 1.0) * u * u), wi * (t * u * u));
+            dst[1] = make_double2(wi * (t * t * (3.0 - 2.0 * t)), wi * (t * t * (t - 1.0)));
+            dst[2] = make_double2(ph * kInv2Pi, cp);
+            dst[3] = make_double2(sp, 0.0);
+        }
+        wave_sync_lds();
+    }
+}
+
+// offsets[b] = sum_{b' < b} counts[b'] for b <= nb (nb buckets), one workgroup
 __global__ __launch_bounds__(1024) void scan_kernel(const unsigned *__restrict__ counts, int nb,
-                                                    int64_t *__restrict__ offsets, unsigned *__restrict__ cursors) {
+                                                    int64_t *__restrict__ offsets) {
     __shared__ int64_t part[1024];
     const int tid = threadIdx.x;
     const int chunk = (nb + 1023) / 1024;
@@ -115,86 +212,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(const unsigned *__restrict__
     for (int b = lo; b < hi; ++b) {
         offsets[b] = run;
         run += counts[b];
-        cursors[b] = 0u;
     }
     if (tid == 1023) offsets[nb] = run;
-}
-
-// Points of the spline region in interval order, one 64-byte record each:
-// (w c_0(t), w c_1(t), w c_2(t), w c_3(t), phi / (2 pi), cos phi, sin phi, 0);
-// polar points (bucket n_int) to their own arrays.  The order inside an
-// interval is the order of the atomic increments.
-__global__ void scatter_kernel(const double *__restrict__ theta, const double *__restrict__ phi,
-                               const double *__restrict__ w, int64_t n, double theta_cut, double h, int n_int,
-                               const double *__restrict__ xn, const int64_t *__restrict__ offsets,
-                               unsigned *__restrict__ cursors, double *__restrict__ q, int64_t n_spline,
-                               double *__restrict__ pth, double *__restrict__ pph, double *__restrict__ pw) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double th = theta[i], ph = phi[i], wi = w[i];
-        const int j = interval_of(th, theta_cut, h, n_int);
-        const int64_t pos = offsets[j] + atomicAdd(&cursors[j], 1u);
-        if (j == n_int) {
-            const int64_t p = pos - offsets[n_int];
-            pth[p] = th;
-            pph[p] = ph;
-            pw[p] = wi;
-            continue;
-        }
-        const double x = cos(th);
-        const double t = (x - xn[j]) / (xn[j + 1] - xn[j]);
-        const double u = 1.0 - t;
-        double sp, cp;
-        sincos(ph, &sp, &cp);
-        double2 *dst = (double2 *)(q + pos * kPointDoubles);
-        dst[0] = make_double2(wi * ((2.0 * t + 1.0) * u * u), wi * (t * u * u));
-        dst[1] = make_double2(wi * (t * t * (3.0 - 2.0 * t)), wi * (t * t * (t - 1.0)));
-        dst[2] = make_double2(ph * kInv2Pi, cp);
-        dst[3] = make_double2(sp, 0.0);
-    }
-}
-
-// The scatter with the same chunks: each workgroup counts its chunk per bucket
-// in LDS, reserves that many places per bucket with one global atomic, then
-// hands out places inside its reservation with LDS atomics.
-__global__ __launch_bounds__(kHistThreads) void scatter_lds_kernel(
-    const double *__restrict__ theta, const double *__restrict__ phi, const double *__restrict__ w, int64_t n,
-    double theta_cut, double h, int n_int, int64_t chunk, const double *__restrict__ xn,
-    const int64_t *__restrict__ offsets, unsigned *__restrict__ cursors, double *__restrict__ q,
-    double *__restrict__ pth, double *__restrict__ pph, double *__restrict__ pw) {
-    extern __shared__ unsigned hist[];
-    const int nb = n_int + 1;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0u;
-    __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * chunk;
-    const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-        atomicAdd(&hist[interval_of(theta[i], theta_cut, h, n_int)], 1u);
-    __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        if (hist[b]) hist[b] = atomicAdd(&cursors[b], hist[b]);   // first place of this workgroup's run
-    __syncthreads();
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const double th = theta[i], ph = phi[i], wi = w[i];
-        const int j = interval_of(th, theta_cut, h, n_int);
-        const int64_t pos = offsets[j] + atomicAdd(&hist[j], 1u);
-        if (j == n_int) {
-            const int64_t p = pos - offsets[n_int];
-            pth[p] = th;
-            pph[p] = ph;
-            pw[p] = wi;
-            continue;
-        }
-        const double x = cos(th);
-        const double t = (x - xn[j]) / (xn[j + 1] - xn[j]);
-        const double u = 1.0 - t;
-        double sp, cp;
-        sincos(ph, &sp, &cp);
-        double2 *dst = (double2 *)(q + pos * kPointDoubles);
-        dst[0] = make_double2(wi * ((2.0 * t + 1.0) * u * u), wi * (t * u * u));
-        dst[1] = make_double2(wi * (t * t * (3.0 - 2.0 * t)), wi * (t * t * (t - 1.0)));
-        dst[2] = make_double2(ph * kInv2Pi, cp);
-        dst[3] = make_double2(sp, 0.0);
-    }
 }
 
 constexpr int kPhaseN = 1024;    // entries of the phase table e^{2 pi i k / kPhaseN}
@@ -676,49 +695,36 @@ SplinePlan spline_plan(int64_t n, int lmax, int n_nodes) {
     // node-sum partials (4 per (l, m) and slice), alpha table, scale table
     p.state_doubles = (size_t)p.ns_slices * 4 * (size_t)tri_size(lmax) + (size_t)coef_table_size(lmax) +
                       (size_t)tri_size(lmax) + 2 * (size_t)kPhaseN;   // + the phase table
-    (void)n;
+    // stable sort: chunks of at least kSortChunkMin points, at most kSortChunksMax of them
+    int64_t chunks = (n + kSortChunkMin - 1) / kSortChunkMin;
+    chunks = chunks < 1 ? 1 : (chunks > kSortChunksMax ? kSortChunksMax : chunks);
+    p.sort_chunk = n > 0 ? (n + chunks - 1) / chunks : 1;
+    p.sort_chunks = n > 0 ? (int)((n + p.sort_chunk - 1) / p.sort_chunk) : 1;
     return p;
 }
 
-hipError_t launch_spline_count(const double *theta, int64_t n, double theta_cut, double h, int n_nodes, double *xn,
-                               double *thn, unsigned *counts, hipStream_t stream) {
+hipError_t launch_spline_sort(const double *theta, const double *phi, const double *w, int64_t n, double theta_cut,
+                              double h, int n_nodes, const SplinePlan &p, double *xn, double *thn, unsigned *H,
+                              unsigned *counts, int64_t *offsets, int64_t *n_polar, double *q, double *pth, double *pph,
+                              double *pw, hipStream_t stream) {
     const int nb = n_nodes;   // n_int intervals + the polar bucket
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, counts, nb);
+    hipLaunchKernelGGL(nodes_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, stream, theta_cut, h, n_nodes, xn, thn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(nodes_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, stream, theta_cut, h, n_nodes, xn, thn);
+    hipLaunchKernelGGL(chunk_hist_kernel, dim3(p.sort_chunks), dim3(64), 0, stream, theta, n, theta_cut, h, nb - 1,
+                       p.sort_chunk, H);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (n > 0) {
-        if (n_nodes <= kHistMax) {
-            const int64_t chunk = (n + kHistBlocks - 1) / kHistBlocks;
-            hipLaunchKernelGGL(count_lds_kernel, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kHistThreads),
-                               sizeof(unsigned) * n_nodes, stream, theta, n, theta_cut, h, n_nodes - 1, chunk, counts);
-        } else {
-            hipLaunchKernelGGL(count_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, n, theta_cut,
-                               h, n_nodes - 1, counts);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-hipError_t launch_spline_scatter(const double *theta, const double *phi, const double *w, int64_t n, double theta_cut,
-                                 double h, int n_nodes, const double *xn, const unsigned *counts, int64_t *offsets,
-                                 unsigned *cursors, double *q, int64_t n_spline, double *pth, double *pph, double *pw,
-                                 hipStream_t stream) {
-    const int nb = n_nodes;
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, counts, nb, offsets, cursors);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n == 0) return e;
-    if (n_nodes <= kHistMax) {
-        const int64_t chunk = (n + kHistBlocks - 1) / kHistBlocks;
-        hipLaunchKernelGGL(scatter_lds_kernel, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kHistThreads),
-                           sizeof(unsigned) * n_nodes, stream, theta, phi, w, n, theta_cut, h, n_nodes - 1, chunk, xn,
-                           (const int64_t *)offsets, cursors, q, pth, pph, pw);
-    } else {
-        hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, stream, theta, phi, w, n, theta_cut,
-                           h, n_nodes - 1, xn, (const int64_t *)offsets, cursors, q, n_spline, pth, pph, pw);
-    }
+    hipLaunchKernelGGL(bucket_total_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, (const unsigned *)H,
+                       p.sort_chunks, nb, counts);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, (const unsigned *)counts, nb, offsets);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(bucket_start_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, H, p.sort_chunks, nb,
+                       (const int64_t *)offsets, n_polar);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(stable_scatter_kernel, dim3(p.sort_chunks), dim3(64), 0, stream, theta, phi, w, n, theta_cut, h,
+                       nb - 1, p.sort_chunk, (const double *)xn, (const int64_t *)offsets, (const unsigned *)H, q, pth,
+                       pph, pw);
     return hipGetLastError();
 }
 

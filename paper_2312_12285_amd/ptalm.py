@@ -64,7 +64,10 @@ _bp_count = _sig("ptalm_bandpower_count", ctypes.c_int, [ctypes.c_int, ctypes.c_
 _bandpowers = _sig("ptalm_bandpowers", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                      ctypes.c_int, ctypes.c_int, _vp, _vp, _vp])
 _alm_spline = _sig("ptalm_alm_from_points_spline", ctypes.c_int,
-                   [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(Opts), _vp])
+                   [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, _vp, ctypes.POINTER(Opts), _vp,
+                    ctypes.c_size_t, _vp])
+_spline_ws = _sig("ptalm_spline_workspace_bytes", ctypes.c_size_t, [_i64, ctypes.c_int, ctypes.c_int])
+_prepare_spline = _sig("ptalm_prepare_spline_call", ctypes.c_int, [_i64, ctypes.c_int, ctypes.c_int])
 _shear = _sig("ptalm_shear_alm_from_points", ctypes.c_int,
               [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.c_int, _vp, _vp, ctypes.POINTER(Opts), _vp])
 _shear_ws = _sig("ptalm_shear_workspace_bytes", ctypes.c_size_t, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
@@ -303,11 +306,21 @@ def bandpowers(cl_hat, M, lmax: int, delta_l: int, lmin: int = 0, mode: int = 0,
     return cb, window
 
 
+def spline_workspace_bytes(n: int, lmax: int, n_nodes: int) -> int:
+    return int(_spline_ws(n, lmax, n_nodes))
+
+
+def prepare_spline_call(n: int, lmax: int, n_nodes: int):
+    """Build the tables a later interpolated transform of these sizes needs (for capture)."""
+    _check(_prepare_spline(n, lmax, n_nodes))
+
+
 def alm_from_points_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: float, out=None,
-                           options: Opts | None = None, stream=None):
+                           options: Opts | None = None, workspace=None, stream=None):
     """a_lm by the interpolated transform of App. A.2 (cubic Hermite splines on n_nodes nodes
     uniform in theta over [theta_cut, pi - theta_cut]; the polar caps by the exact sum).
-    Same layout as alm_from_points with one weight vector."""
+    Same layout as alm_from_points with one weight vector.  workspace: optional device
+    buffer of spline_workspace_bytes(n, lmax, n_nodes) bytes (then nothing is allocated)."""
     _dev_f64(theta, "theta"); _dev_f64(phi, "phi"); _dev_f64(w, "w")
     n = theta.numel()
     if phi.numel() != n or w.numel() != n:
@@ -319,8 +332,9 @@ def alm_from_points_spline(theta, phi, w, lmax: int, n_nodes: int, theta_cut: fl
         _dev_f64(out, "out")
         if out.numel() != 2 * T:
             raise ValueError("out has the wrong size")
+    ws_ptr, ws_len = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
     _check(_alm_spline(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, n_nodes, float(theta_cut), _ptr(out),
-                       None if options is None else ctypes.byref(options), _stream(stream)))
+                       None if options is None else ctypes.byref(options), ws_ptr, ws_len, _stream(stream)))
     return out
 
 

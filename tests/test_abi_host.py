@@ -159,14 +159,38 @@ def test_spline_rejects_point_counts_above_its_counters(lib):
     f = lib.ptalm_alm_from_points_spline
     f.restype = ctypes.c_int
     f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                  ctypes.c_void_p]
     lib.ptalm_last_error.restype = ctypes.c_char_p
     fake = 1 << 40
-    assert f(fake, fake, fake, 2 ** 32, 64, 100, 0.01, fake, None, None) == -1
+    assert f(fake, fake, fake, 2 ** 32, 64, 100, 0.01, fake, None, None, 0, None) == -1
     assert b"PTALM_SPLINE_N_MAX" in lib.ptalm_last_error()
-    assert f(fake, fake, fake, -1, 64, 100, 0.01, fake, None, None) == -1
-    assert f(fake, fake, fake, 10, 64, 1, 0.01, fake, None, None) == -1           # n_nodes < 2
-    assert f(fake, fake, fake, 10, 64, 100, 2.0, fake, None, None) == -1          # theta_cut >= pi/2
+    assert f(fake, fake, fake, -1, 64, 100, 0.01, fake, None, None, 0, None) == -1
+    assert f(fake, fake, fake, 10, 64, 1, 0.01, fake, None, None, 0, None) == -1           # n_nodes < 2
+    assert f(fake, fake, fake, 10, 64, 100, 2.0, fake, None, None, 0, None) == -1          # theta_cut >= pi/2
+
+
+def test_spline_workspace_is_sized_and_checked(lib):
+    """The interpolated transform's scratch size grows with n, lmax and the nodes; a caller
+    workspace that is too small or misaligned is refused before any device call."""
+    ws = lib.ptalm_spline_workspace_bytes
+    ws.restype = ctypes.c_size_t
+    ws.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+    a, b = ws(10_000, 64, 100), ws(20_000, 64, 100)
+    assert a > 0 and b - a >= 88 * 10_000          # records and polar arrays for every point
+    assert ws(10_000, 128, 100) > a and ws(10_000, 64, 200) > a
+    assert ws(-1, 64, 100) == 0 and ws(10, 64, 1) == 0 and ws(10, 16384, 100) == 0
+    f = lib.ptalm_alm_from_points_spline
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                  ctypes.c_void_p]
+    lib.ptalm_last_error.restype = ctypes.c_char_p
+    fake = 1 << 40
+    assert f(fake, fake, fake, 10_000, 64, 100, 0.01, fake, None, fake, a - 1, None) == -1
+    assert b"too small" in lib.ptalm_last_error()
+    assert f(fake, fake, fake, 10_000, 64, 100, 0.01, fake, None, fake + 8, a, None) == -1
+    assert b"aligned" in lib.ptalm_last_error()
 
 
 def test_spectra_and_axpy_reject_overlapping_outputs(lib):
