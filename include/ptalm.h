@@ -287,8 +287,31 @@ int ptalm_last_timing(double *transform_ms);
 
 /* Builds, on the current device, the coefficient tables the transform uses for
  * this lmax (normally built on first use, synchronously).  Lets a caller keep
- * that one-off cost out of a timed region or a latency-sensitive loop. */
+ * that one-off cost out of a timed region or a latency-sensitive loop.  Also the
+ * set-up of ptalm_alm_from_points_noalloc for this lmax (its m-range table and
+ * the address of its static scratch on this device). */
 int ptalm_prepare(int lmax);
+
+/*
+ * No-allocation form of ptalm_alm_from_points, for callers that cannot
+ * allocate device memory at call time: code being captured into a HIP graph,
+ * tight serving loops, hosts that forbid allocation after set-up.  Same
+ * arguments, result and FP64 arithmetic as ptalm_alm_from_points (eq. alm_def);
+ * the per-slice partial sums go to a static device array of
+ * PTALM_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends, so the call allocates nothing and synchronizes
+ * nothing.  Set-up: ptalm_prepare(lmax) must have been called on the current
+ * device for this lmax (it builds the tables and looks up the array's address);
+ * otherwise PTALM_EBUSY.  Limits: lmax <= PTALM_NOALLOC_LMAX_MAX (one slice of
+ * partials, 16*T bytes, must fit the array), else PTALM_EINVAL.  Every call on
+ * one device shares that device's array: calls that overlap in time on one
+ * device (different streams without ordering between them) race and give wrong
+ * results; order them on one stream or synchronize in between.
+ */
+#define PTALM_NOALLOC_SCRATCH_BYTES (128u << 20)
+#define PTALM_NOALLOC_LMAX_MAX 4094
+int ptalm_alm_from_points_noalloc(const double *theta, const double *phi, const double *w,
+                                  int64_t n, int lmax, double *alm, void *stream);
 
 /* Builds everything the call ptalm_alm_from_points_ex(n, lmax, opts, ...)
  * would build on first use (coefficient tables, m-range table), so that the

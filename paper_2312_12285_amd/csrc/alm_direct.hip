@@ -37,12 +37,42 @@
 // costs about one add per reduced value per lane, i.e. a fraction ~2/(3.5 KP)
 // of the inner loop, and moves 64*sizeof(AccT) bytes of LDS per value and lane
 // group (half with the register stage), which is what limits small KP.
+#include <map>
+#include <mutex>
 #include <type_traits>
 
+#include "ptalm.h"
 #include "ptalm_internal.h"
 #include "wave_common.h"
 
+// Static scratch of the no-allocation transform (ptalm_alm_from_points_noalloc):
+// the slice partials live here instead of in memory the call allocates.  Every
+// device the library runs on holds its own copy until the process ends.  In host
+// code this name is only a handle: the device address comes from
+// hipGetSymbolAddress (noalloc_scratch below), never from the name itself.
+static __device__ __align__(256) unsigned char scratch[PTALM_NOALLOC_SCRATCH_BYTES];
+
 namespace ptalm {
+
+// Device address of `scratch` on the current device, looked up once per device
+// with that device current and kept for later calls.
+hipError_t noalloc_scratch(void **out) {
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    int dev;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
 
 namespace {
 

@@ -228,6 +228,11 @@ int resolve(int64_t n, int lmax, const ptalm_opts *o, Resolved *r) {
     return PTALM_OK;
 }
 
+// Plan of the no-allocation transform: the default FP64 kernel variant, m ranges
+// fixed by lmax alone (one range table per lmax, built by ptalm_prepare), and as
+// many point slices (up to kMaxSlices) as the static scratch holds.
+int noalloc_ranges(int lmax) { return std::min(lmax + 1, 2048); }
+
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t partial_bytes(const Resolved &r, int lmax) {
@@ -842,7 +847,64 @@ int ptalm_prepare(int lmax) {
     g_error.clear();
     if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
     const ptalm::Tables *tab;
-    return get_tables(lmax, &tab);
+    int rc = get_tables(lmax, &tab);
+    if (rc || lmax > PTALM_NOALLOC_LMAX_MAX) return rc;
+    // set-up of the no-allocation form: its range table and its scratch address
+    const int *ranges;
+    if ((rc = get_ranges(lmax, noalloc_ranges(lmax), &ranges))) return rc;
+    void *sp;
+    hipError_t e = ptalm::noalloc_scratch(&sp);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "hipGetSymbolAddress(scratch)");
+}
+
+int ptalm_alm_from_points_noalloc(const double *theta, const double *phi, const double *w, int64_t n, int lmax,
+                                  double *alm, void *stream_) {
+    g_error.clear();
+    if (n < 0) return fail(PTALM_EINVAL, "n < 0");
+    if (!lmax_ok(lmax)) return fail(PTALM_EINVAL, "lmax out of range");
+    if (lmax > PTALM_NOALLOC_LMAX_MAX)
+        return fail(PTALM_EINVAL, "lmax above PTALM_NOALLOC_LMAX_MAX (4094): one slice of partials, 16*T bytes, "
+                                  "must fit the 128 MiB static scratch");
+    if (alm == nullptr) return fail(PTALM_EINVAL, "alm is NULL");
+    if (n > 0 && (theta == nullptr || phi == nullptr || w == nullptr)) return fail(PTALM_EINVAL, "NULL input");
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t T = ptalm::tri_size(lmax);
+    hipError_t e;
+    if (n == 0) {
+        e = ptalm::launch_zero(alm, 2 * T, stream);
+        return e == hipSuccess ? PTALM_OK : fail_hip(e, "zero kernel launch");
+    }
+    const ptalm::Tables *tab;
+    const int *ranges;
+    const int R = noalloc_ranges(lmax);
+    if (get_tables(lmax, &tab, false) != PTALM_OK || get_ranges(lmax, R, &ranges, false) != PTALM_OK)
+        return fail(PTALM_EBUSY, "not set up for this lmax on this device: call ptalm_prepare(lmax) first");
+    void *sp = nullptr;
+    if ((e = ptalm::noalloc_scratch(&sp)) != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    const int64_t groups = (n + 64 * kDefaultKP - 1) / (64 * kDefaultKP);
+    const int64_t fit = (int64_t)(PTALM_NOALLOC_SCRATCH_BYTES / (sizeof(double) * 2 * (size_t)T));
+    const int S = (int)std::min<int64_t>(std::min<int64_t>(kMaxSlices, groups), fit);
+    ptalm::AlmArgs a;
+    a.theta = theta;
+    a.phi = phi;
+    a.w = w;
+    a.n = n;
+    a.lmax = lmax;
+    a.n_ranges = R;
+    a.n_slices = S;
+    a.groups = groups;
+    a.range_m = ranges;
+    a.coef = tab->coef;
+    a.coef32 = tab->coef32;
+    a.partial = (double *)sp;   // the static scratch: S x 2T doubles, every one written before it is read
+    a.w_stride = n;
+    a.n_weights = 1;
+    bool supported = true;
+    e = ptalm::launch_alm_fp64(a, kDefaultKP, kDefaultLB, kDefaultMode, stream, &supported);
+    if (!supported) return fail(PTALM_ENOTSUP, "default kernel variant not compiled");
+    if (e != hipSuccess) return fail_hip(e, "transform kernel launch");
+    e = ptalm::launch_reduce_partials(a.partial, S, tab->sigma, lmax, alm, stream);
+    return e == hipSuccess ? PTALM_OK : fail_hip(e, "reduce kernel launch");
 }
 
 int ptalm_prepare_call(int64_t n, int lmax, const ptalm_opts *opts) {

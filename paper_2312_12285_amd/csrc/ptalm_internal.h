@@ -103,6 +103,7 @@ hipError_t build_tables(int lmax, Tables *t, hipStream_t stream);
 hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
 hipError_t launch_alm_mixed(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
 hipError_t launch_alm_fp32(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
+hipError_t noalloc_scratch(void **out);   // device address of the static scratch (alm_direct.hip)
 hipError_t launch_reduce_partials(const double *partial, int n_slices, const double *sigma, int lmax,
                                   double *alm, hipStream_t stream);
 hipError_t launch_cl(const double *alm1, const double *alm2, int lmax, double *cl, hipStream_t stream);

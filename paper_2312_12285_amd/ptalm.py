@@ -48,6 +48,9 @@ _alm_index = _sig("ptalm_alm_index", _i64, [ctypes.c_int, ctypes.c_int, ctypes.c
 _alm = _sig("ptalm_alm_from_points", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, _vp, _vp])
 _alm_ex = _sig("ptalm_alm_from_points_ex", ctypes.c_int,
                [_vp, _vp, _vp, _i64, ctypes.c_int, _vp, ctypes.POINTER(Opts), _vp, ctypes.c_size_t, _vp])
+_alm_noalloc = _sig("ptalm_alm_from_points_noalloc", ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, _vp, _vp])
+NOALLOC_SCRATCH_BYTES = 128 << 20
+NOALLOC_LMAX_MAX = 4094
 _ws_bytes = _sig("ptalm_workspace_bytes", ctypes.c_size_t, [_i64, ctypes.c_int, ctypes.POINTER(Opts)])
 _cl = _sig("ptalm_cl_from_alm", ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp])
 _cross = _sig("ptalm_cross_cl", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp])
@@ -195,6 +198,20 @@ def alm_from_points(theta, phi, w, lmax: int, out=None, options: Opts | None = N
         ws_ptr, ws_len = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
         _check(_alm_ex(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, _ptr(out), ctypes.byref(o), ws_ptr, ws_len,
                        _stream(stream)))
+    return out
+
+
+def alm_from_points_noalloc(theta, phi, w, lmax: int, out, stream=None):
+    """The no-allocation transform (FP64, one weight vector): the library's static scratch
+    holds the partial sums, so the call allocates nothing; `out` (2T doubles) must be given and
+    prepare(lmax) must have run on this device.  Calls on one device must not overlap in time."""
+    _dev_f64(theta, "theta"); _dev_f64(phi, "phi"); _dev_f64(w, "w"); _dev_f64(out, "out")
+    n = theta.numel()
+    if phi.numel() != n or w.numel() != n:
+        raise ValueError("theta, phi and w must have the same length")
+    _lmax_ok(lmax)
+    _need(out, 2 * alm_size(lmax), "out")
+    _check(_alm_noalloc(_ptr(theta), _ptr(phi), _ptr(w), n, lmax, _ptr(out), _stream(stream)))
     return out
 
 
