@@ -335,13 +335,18 @@ int ptalm_autotune(const double *theta, const double *phi, const double *w, int6
  * Request server: continuous batching of transforms on one device (host API).
  *
  * A server owns an arena of device memory (the scratch budget) and `slots`
- * HIP streams.  Submitted requests wait in arrival order; a scheduler thread
- * admits the oldest one as soon as a slot is free and its scratch footprint
- * (ptalm_workspace_bytes of its call) fits in the arena, enqueues its
- * transform (and spectrum) on the slot's stream, and frees slot and memory
- * when the work completes.  Requests admitted while others run execute
- * concurrently on the device.  Each request uses the work plan of the same
- * call made alone, so its a_lm are bitwise those of the solo call.
+ * HIP streams.  A scheduler thread admits submitted requests into the arena
+ * (their scratch footprint, ptalm_workspace_bytes of their call) in arrival
+ * order, letting later requests that fit pass one that does not until it has
+ * waited 2 s.  Each admitted request runs as work items: launches of its
+ * transform over consecutive groups of its point slices (about 2e11 terms
+ * each), then one finishing launch (the second pass and the spectrum).  Items
+ * go to free slots, requests waiting longer than 2 s first (oldest first),
+ * then the one with the least remaining work, so small requests do not wait
+ * behind large ones; items of different requests run concurrently on the
+ * device.  Each request uses the work plan of the same call made alone and
+ * its chunks compute exactly that call's slice partials, so its a_lm are
+ * bitwise those of the solo call.
  * The catalog and output buffers are device memory owned by the caller: the
  * inputs must be complete before ptalm_server_submit and stay valid, and the
  * outputs untouched, until the request completes.
@@ -359,7 +364,7 @@ typedef struct ptalm_request {
 
 typedef struct ptalm_request_stats {
     int status;                /* PTALM_OK or the error of the request                 */
-    int slot;                  /* stream slot it ran on                                */
+    int slot;                  /* stream slot of its first work item                   */
     size_t footprint_bytes;    /* arena bytes held from admission to completion        */
     double submit_s, admit_s, done_s;   /* steady (CLOCK_MONOTONIC) clock, seconds:
                                            submission, admission, completion seen      */
@@ -367,8 +372,8 @@ typedef struct ptalm_request_stats {
 
 typedef struct ptalm_server_state {
     size_t arena_bytes, arena_in_use;
-    int slots, running;
-    int64_t waiting;
+    int slots, running;        /* running: requests admitted and not yet complete   */
+    int64_t waiting;           /* waiting: submitted requests not yet admitted       */
 } ptalm_server_state;
 
 /* Creates a server on `device` with an arena of arena_bytes (allocated now)

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64) void alm_direct_kernel(AlmArgs args) {
     const int lane = threadIdx.x;
     const int lmax = args.lmax;
     const int r = blockIdx.x % args.n_ranges;
-    const int s = blockIdx.x / args.n_ranges;
+    const int s = args.slice_base + (int)(blockIdx.x / args.n_ranges);
     // wave-uniform: keeps everything derived from m in scalar registers, so the
     // step coefficients below are fetched with scalar loads
     const int m_a = __builtin_amdgcn_readfirstlane(args.range_m[r]);
@@ -322,7 +322,7 @@ __global__ void reduce_partials_kernel(const double *__restrict__ partial, int n
 
 template <typename RecT, typename AccT, int KP, int LB, int SWAP, int PIPE>
 hipError_t launch_one(const AlmArgs &a, hipStream_t stream) {
-    const int blocks = a.n_ranges * a.n_slices;
+    const int blocks = a.n_ranges * (a.slice_count > 0 ? a.slice_count : a.n_slices);
     hipLaunchKernelGGL((alm_direct_kernel<RecT, AccT, KP, LB, SWAP, PIPE>), dim3(blocks), dim3(64), 0, stream, a);
     return hipGetLastError();
 }

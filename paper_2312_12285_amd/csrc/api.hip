@@ -1043,3 +1043,81 @@ int ptalm_release_cache(void) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Request-server support: one transform planned exactly as
+// ptalm_alm_from_points_ex(opts = {precision}) plans it, launched in chunks of
+// point slices and then the second pass.  A slice's partial is computed by the
+// same work items whichever launch runs them, so the result is bitwise that of
+// the single call.
+// ---------------------------------------------------------------------------
+namespace ptalm {
+
+int sliced_slice_count(int64_t n, int lmax, int precision) {
+    if (n < 0 || !lmax_ok(lmax)) return fail(PTALM_EINVAL, "bad n or lmax");
+    ptalm_opts o;
+    memset(&o, 0, sizeof o);
+    o.precision = precision;
+    o.n_weights = 1;
+    Resolved r;
+    const int rc = resolve(n, lmax, &o, &r);
+    return rc ? rc : r.S;
+}
+
+int plan_sliced(const double *theta, const double *phi, const double *w, int64_t n, int lmax, int precision,
+                double *partial, SlicedCall *c) {
+    g_error.clear();
+    if (n <= 0 || !lmax_ok(lmax)) return fail(PTALM_EINVAL, "bad n or lmax");
+    if (precision != PTALM_FP64 && precision != PTALM_MIXED && precision != PTALM_FP32)
+        return fail(PTALM_EINVAL, "sliced calls take the vector forms");
+    ptalm_opts o;
+    memset(&o, 0, sizeof o);
+    o.precision = precision;
+    o.n_weights = 1;
+    Resolved r;
+    int rc = resolve(n, lmax, &o, &r);
+    if (rc) return rc;
+    const Tables *tab;
+    const int *ranges;
+    if ((rc = get_tables(lmax, &tab)) || (rc = get_ranges(lmax, r.R, &ranges))) return rc;
+    AlmArgs &a = c->a;
+    a = AlmArgs();
+    a.theta = theta;
+    a.phi = phi;
+    a.w = w;
+    a.n = n;
+    a.lmax = lmax;
+    a.n_ranges = r.R;
+    a.n_slices = r.S;
+    a.groups = r.groups;
+    a.range_m = ranges;
+    a.coef = tab->coef;
+    a.coef32 = tab->coef32;
+    a.partial = partial;
+    a.w_stride = n;
+    a.n_weights = 1;
+    c->precision = precision;
+    c->kp = r.kp;
+    c->lb = r.lb;
+    c->mode = r.mode;
+    c->sigma = tab->sigma;
+    return PTALM_OK;
+}
+
+hipError_t launch_sliced(const SlicedCall &c, int s0, int s1, hipStream_t stream) {
+    if (s0 < 0 || s1 > c.a.n_slices || s0 >= s1) return hipErrorInvalidValue;
+    AlmArgs a = c.a;
+    a.slice_base = s0;
+    a.slice_count = s1 - s0;
+    bool supported = true;
+    const hipError_t e = c.precision == PTALM_FP64    ? launch_alm_fp64(a, c.kp, c.lb, c.mode, stream, &supported)
+                         : c.precision == PTALM_MIXED ? launch_alm_mixed(a, c.kp, c.lb, c.mode, stream, &supported)
+                                                      : launch_alm_fp32(a, c.kp, c.lb, c.mode, stream, &supported);
+    return supported ? e : hipErrorInvalidKernelFile;
+}
+
+hipError_t launch_sliced_finish(const SlicedCall &c, double *alm, hipStream_t stream) {
+    return launch_reduce_partials(c.a.partial, c.a.n_slices, c.sigma, c.a.lmax, alm, stream);
+}
+
+}  // namespace ptalm

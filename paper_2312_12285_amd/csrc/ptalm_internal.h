@@ -69,6 +69,20 @@ struct AlmArgs {
     // when set, the number of points is read here on the device (n and groups
     // above are then upper bounds used only by the plan)
     const int64_t *n_dev = nullptr;
+    // slices [slice_base, slice_base + slice_count) of the n_slices of the plan are
+    // launched (slice_count 0: all of them); the request server runs a call this way
+    // in chunks, each computing exactly the partials the whole launch computes
+    int slice_base = 0;
+    int slice_count = 0;
+};
+
+// One transform planned as ptalm_alm_from_points_ex would run it (same kernel
+// variant, slices and ranges, tables built), for launching in chunks of point
+// slices followed by the second pass.
+struct SlicedCall {
+    AlmArgs a;
+    int precision = 0, kp = 0, lb = 0, mode = 0;
+    const double *sigma = nullptr;
 };
 
 // Arguments of the multi-weight MFMA kernels.
@@ -104,6 +118,15 @@ hipError_t launch_alm_fp64(const AlmArgs &a, int kp, int lb, int mode, hipStream
 hipError_t launch_alm_mixed(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
 hipError_t launch_alm_fp32(const AlmArgs &a, int kp, int lb, int mode, hipStream_t stream, bool *supported);
 hipError_t noalloc_scratch(void **out);   // device address of the static scratch (alm_direct.hip)
+
+// request server support (api.hip): the slice count the call would use, the
+// plan itself (tables built on first use; `partial` is its scratch), one chunk
+// of slices, and the second pass into alm
+int sliced_slice_count(int64_t n, int lmax, int precision);
+int plan_sliced(const double *theta, const double *phi, const double *w, int64_t n, int lmax, int precision,
+                double *partial, SlicedCall *c);
+hipError_t launch_sliced(const SlicedCall &c, int s0, int s1, hipStream_t stream);
+hipError_t launch_sliced_finish(const SlicedCall &c, double *alm, hipStream_t stream);
 hipError_t launch_reduce_partials(const double *partial, int n_slices, const double *sigma, int lmax,
                                   double *alm, hipStream_t stream);
 hipError_t launch_cl(const double *alm1, const double *alm2, int lmax, double *cl, hipStream_t stream);

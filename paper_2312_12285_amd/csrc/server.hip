@@ -2,18 +2,23 @@
 //
 // Requests (a catalog already resident in device memory, its lmax and
 // precision, and where to write a_lm and optionally C_l) are queued by
-// ptalm_server_submit from any host thread.  A scheduler thread admits them in
-// arrival order as soon as an execution slot (a HIP stream of default
-// priority) is free and their scratch footprint fits in the server's device
-// arena (server_core.h), enqueues the transform (and spectrum) on the slot's
-// stream with its arena block as workspace, and detects completion by polling
-// an event per request; completion frees the slot and the block and wakes the
-// waiters.  Requests admitted while others run execute concurrently on the
-// device.  Every request is computed with the same work plan as the same call
-// made alone, so its result is bitwise the solo result.
+// ptalm_server_submit from any host thread.  A scheduler thread admits them
+// into the server's device arena (their scratch block) and runs each as work
+// items (server_core.h): launches of the transform over consecutive groups of
+// its point slices, then one finishing launch (the second pass and the
+// spectrum) once every chunk has completed.  Items go to execution slots (HIP
+// streams of default priority) as they free up, shortest remaining work first,
+// so a small request does not wait behind a large one, and requests that have
+// waited long go first, so none starves.  Completion of an item is seen by
+// polling an event.  Every request uses the work plan of the same call made
+// alone; a chunk computes exactly the slice partials that call computes, so the
+// result is bitwise the solo result.
+#include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <mutex>
 #include <string>
@@ -31,13 +36,23 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// terms of work per chunk aimed at (~35 ms of the whole device in FP64)
+constexpr double kChunkTerms = 2e11;
+// a request waiting longer than this (from submission) goes before shorter work
+constexpr double kAgeSeconds = 2.0;
+
 struct Req {
     ptalm_request r;
     ptalm_request_stats st;
-    ptalm::serve::Admitted adm{};
-    hipEvent_t done_ev = nullptr;
-    bool done = false;
+    ptalm::SlicedCall call{};
+    int chunks = 0, slices_per_chunk = 1;
+    bool planned = false, failed = false, done = false;
     std::string err;
+};
+
+struct InFlight {
+    ptalm::serve::Item it;
+    hipEvent_t ev;
 };
 
 }  // namespace
@@ -48,14 +63,15 @@ struct ptalm_server {
     std::vector<hipStream_t> streams;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    ptalm::serve::Admission adm;
+    ptalm::serve::Scheduler sched;
     std::unordered_map<int64_t, Req> reqs;
-    std::vector<int64_t> inflight;
+    std::vector<InFlight> inflight;
+    std::vector<hipEvent_t> spare_events;
     int64_t next_ticket = 1;
     bool stop = false;
     std::thread th;
 
-    ptalm_server(size_t bytes, int slots) : adm(bytes, slots) {}
+    ptalm_server(size_t bytes, int slots) : sched(bytes, slots, kAgeSeconds) {}
 };
 
 namespace {
@@ -76,27 +92,27 @@ size_t footprint(const ptalm_request &r) {
     return ptalm_workspace_bytes(r.n, r.lmax, &o);
 }
 
-// Enqueues one admitted request on its slot's stream (scheduler thread, no lock held).
-void launch(ptalm_server *s, Req &q) {
-    hipStream_t st = s->streams[q.adm.slot];
-    ptalm_opts o;
-    memset(&o, 0, sizeof o);
-    o.precision = q.r.precision;
-    o.n_weights = 1;
-    void *ws = (char *)s->arena + q.adm.offset;
-    int rc = ptalm_alm_from_points_ex(q.r.theta, q.r.phi, q.r.w, q.r.n, q.r.lmax, q.r.alm, &o, ws, q.adm.bytes, st);
-    if (rc == PTALM_OK && q.r.cl != nullptr) rc = ptalm_cl_from_alm(q.r.alm, q.r.lmax, q.r.cl, st);
-    if (rc == PTALM_OK) {
-        hipError_t e = hipEventCreateWithFlags(&q.done_ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(q.done_ev, st);
-        if (e != hipSuccess) {
-            rc = PTALM_EDEVICE;
-            q.err = std::string("completion event: ") + hipGetErrorString(e);
-        }
+// Enqueues one work item on its slot's stream (scheduler thread, no lock held).
+// Returns the HIP or ptalm error, with the message in q.err.
+int launch(ptalm_server *s, Req &q, const ptalm::serve::Item &it) {
+    hipStream_t st = s->streams[it.slot];
+    hipError_t e = hipSuccess;
+    if (it.chunk != ptalm::serve::kFinish) {
+        const int s0 = it.chunk * q.slices_per_chunk;
+        const int s1 = std::min(q.call.a.n_slices, s0 + q.slices_per_chunk);
+        e = ptalm::launch_sliced(q.call, s0, s1, st);
+    } else if (q.r.n == 0) {
+        e = ptalm::launch_zero(q.r.alm, 2 * ptalm::tri_size(q.r.lmax), st);
     } else {
-        q.err = ptalm_last_error();
+        e = ptalm::launch_sliced_finish(q.call, q.r.alm, st);
     }
-    q.st.status = rc;
+    if (e == hipSuccess && it.chunk == ptalm::serve::kFinish && q.r.cl != nullptr)
+        e = ptalm::launch_cl(q.r.alm, nullptr, q.r.lmax, q.r.cl, st);
+    if (e != hipSuccess) {
+        q.err = std::string("launch: ") + hipGetErrorString(e);
+        return PTALM_EDEVICE;
+    }
+    return PTALM_OK;
 }
 
 void scheduler(ptalm_server *s) {
@@ -104,35 +120,69 @@ void scheduler(ptalm_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         bool progress = false;
-        // 1. admissions, in arrival order
-        std::vector<ptalm::serve::Admitted> adm = s->adm.admit();
-        if (!adm.empty()) {
+        const double t = now_s();
+        // 1. memory admission; plan each admitted request (tables built on first use)
+        for (const ptalm::serve::Admitted &a : s->sched.admit(t)) {
             progress = true;
-            const double t = now_s();
-            std::vector<Req *> batch;
-            for (const auto &a : adm) {
-                Req &q = s->reqs[a.ticket];
-                q.adm = a;
-                q.st.admit_s = t;
-                q.st.slot = a.slot;
-                q.st.footprint_bytes = a.bytes;
-                batch.push_back(&q);
+            Req &q = s->reqs[a.ticket];
+            q.st.admit_s = t;
+            q.st.footprint_bytes = a.bytes;
+            if (q.r.n > 0) {
+                lk.unlock();
+                const int rc = ptalm::plan_sliced(q.r.theta, q.r.phi, q.r.w, q.r.n, q.r.lmax, q.r.precision,
+                                                  (double *)((char *)s->arena + a.offset), &q.call);
+                lk.lock();
+                if (rc != PTALM_OK) {
+                    q.failed = true;
+                    q.st.status = rc;
+                    q.err = ptalm_last_error();
+                }
             }
-            lk.unlock();
-            for (Req *q : batch) launch(s, *q);   // map entries are stable while in flight
-            lk.lock();
-            for (Req *q : batch) s->inflight.push_back(q->adm.ticket);
         }
-        // 2. completions
+        // 2. work items onto free slots
+        ptalm::serve::Item it;
+        while (s->sched.next_item(t, &it)) {
+            progress = true;
+            Req &q = s->reqs[it.ticket];
+            if (it.chunk == 0 || (it.chunk == ptalm::serve::kFinish && q.st.slot < 0)) q.st.slot = it.slot;
+            hipEvent_t ev = nullptr;
+            if (!q.failed) {
+                lk.unlock();
+                int rc = launch(s, q, it);
+                if (rc == PTALM_OK) {
+                    hipError_t e = hipSuccess;
+                    if (s->spare_events.empty()) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                    else {
+                        ev = s->spare_events.back();
+                        s->spare_events.pop_back();
+                    }
+                    if (e == hipSuccess) e = hipEventRecord(ev, s->streams[it.slot]);
+                    if (e != hipSuccess) {
+                        rc = PTALM_EDEVICE;
+                        q.err = std::string("completion event: ") + hipGetErrorString(e);
+                    }
+                }
+                lk.lock();
+                if (rc != PTALM_OK) {
+                    q.failed = true;
+                    q.st.status = rc;
+                }
+            }
+            s->inflight.push_back({it, q.failed ? nullptr : ev});
+            if (q.failed && ev) s->spare_events.push_back(ev);
+        }
+        // 3. completions
         for (size_t i = 0; i < s->inflight.size();) {
-            Req &q = s->reqs[s->inflight[i]];
-            bool finished = q.st.status != PTALM_OK;   // failed at launch
+            InFlight &f = s->inflight[i];
+            Req &q = s->reqs[f.it.ticket];
+            bool finished = f.ev == nullptr;   // never launched (the request failed)
             if (!finished) {
-                const hipError_t e = hipEventQuery(q.done_ev);
+                const hipError_t e = hipEventQuery(f.ev);
                 if (e == hipSuccess) {
                     finished = true;
                 } else if (e != hipErrorNotReady) {
                     finished = true;
+                    q.failed = true;
                     q.st.status = PTALM_EDEVICE;
                     q.err = std::string("device error: ") + hipGetErrorString(e);
                 }
@@ -141,19 +191,17 @@ void scheduler(ptalm_server *s) {
                 ++i;
                 continue;
             }
-            if (q.done_ev) {
-                hipEventDestroy(q.done_ev);
-                q.done_ev = nullptr;
+            if (f.ev) s->spare_events.push_back(f.ev);
+            if (s->sched.item_done(f.it)) {
+                q.st.done_s = now_s();
+                q.done = true;
             }
-            q.st.done_s = now_s();
-            q.done = true;
-            s->adm.complete(q.adm);
             s->inflight[i] = s->inflight.back();
             s->inflight.pop_back();
             progress = true;
         }
         if (progress) s->cv_done.notify_all();
-        if (s->stop && s->adm.waiting() == 0 && s->inflight.empty()) break;
+        if (s->stop && s->sched.waiting() == 0 && s->sched.active() == 0 && s->inflight.empty()) break;
         if (!progress) {
             // idle or waiting on the device: short sleep, woken early by a submission
             s->cv_work.wait_for(lk, std::chrono::microseconds(s->inflight.empty() ? 2000 : 50));
@@ -181,7 +229,7 @@ int ptalm_server_create(int device, size_t arena_bytes, int slots, ptalm_server 
     ptalm_server *s = new ptalm_server(arena_bytes, slots);
     s->device = device;
     int rc = PTALM_OK;
-    if ((e = hipMalloc(&s->arena, s->adm.arena().size())) != hipSuccess)
+    if ((e = hipMalloc(&s->arena, s->sched.arena().size())) != hipSuccess)
         rc = sfail(e == hipErrorOutOfMemory ? PTALM_ENOMEM : PTALM_EDEVICE, "arena allocation failed");
     for (int i = 0; i < slots && rc == PTALM_OK; ++i) {
         hipStream_t st;
@@ -212,13 +260,27 @@ int ptalm_server_submit(ptalm_server *s, const ptalm_request *req, int64_t *tick
         return sfail(PTALM_EINVAL, "NULL pointer in request");
     const size_t bytes = req->n > 0 ? footprint(*req) : ptalm::serve::kArenaAlign;
     if (bytes == 0) return sfail(PTALM_EINVAL, ptalm_last_error());
+    // work items: chunks of about kChunkTerms terms, whole slices of the call's plan
+    int chunks = 0, per_chunk = 1;
+    double chunk_work = 0.0;
+    if (req->n > 0) {
+        const int S = ptalm::sliced_slice_count(req->n, req->lmax, req->precision);
+        if (S < 1) return sfail(PTALM_EINVAL, ptalm_last_error());
+        const double work = (double)req->n * (double)ptalm::tri_size(req->lmax);
+        per_chunk = (int)std::min<double>(S, std::max(1.0, std::ceil(S * kChunkTerms / work)));
+        chunks = (S + per_chunk - 1) / per_chunk;
+        chunk_work = work * per_chunk / S;
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return sfail(PTALM_EINVAL, "server is shutting down");
     const int64_t t = s->next_ticket;
-    if (!s->adm.push(t, bytes)) return sfail(PTALM_EBUSY, "request footprint exceeds the server arena");
+    if (!s->sched.push(t, bytes, chunks, chunk_work, now_s()))
+        return sfail(PTALM_EBUSY, "request footprint exceeds the server arena");
     ++s->next_ticket;
     Req &q = s->reqs[t];
     q.r = *req;
+    q.chunks = chunks;
+    q.slices_per_chunk = per_chunk;
     memset(&q.st, 0, sizeof q.st);
     q.st.status = PTALM_OK;
     q.st.slot = -1;
@@ -267,11 +329,11 @@ int ptalm_server_query(ptalm_server *s, ptalm_server_state *info) {
     g_server_error.clear();
     if (s == nullptr || info == nullptr) return sfail(PTALM_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    info->arena_bytes = s->adm.arena().size();
-    info->arena_in_use = s->adm.arena().in_use();
-    info->slots = s->adm.slots();
-    info->running = s->adm.running();
-    info->waiting = (int64_t)s->adm.waiting();
+    info->arena_bytes = s->sched.arena().size();
+    info->arena_in_use = s->sched.arena().in_use();
+    info->slots = s->sched.slots();
+    info->running = (int)s->sched.active();
+    info->waiting = (int64_t)s->sched.waiting();
     return PTALM_OK;
 }
 
@@ -287,6 +349,7 @@ int ptalm_server_destroy(ptalm_server *s) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
+    for (hipEvent_t ev : s->spare_events) hipEventDestroy(ev);
     for (hipStream_t st : s->streams) hipStreamDestroy(st);
     hipFree(s->arena);
     (void)hipSetDevice(prev);

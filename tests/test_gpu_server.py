@@ -6,6 +6,9 @@
   request keeps its solo work plan); two of them also pass the oracle gate.
 * With an arena smaller than the mix, admission never holds more scratch than
   the arena, admits in arrival order, and still completes everything.
+* Requests run as work items (chunks of point slices): a small request
+  submitted behind two large ones completes first, and all three are bitwise
+  their solo results.
 * Requests that can never fit, or that ask for a form the server does not
   run, are refused at submission; destroying a server completes pending work.
 """
@@ -100,6 +103,24 @@ def test_admission_budget_and_order(lib):
     admits = [s.admit_s for s in stats]   # tickets were submitted in list order
     assert all(a <= b for a, b in zip(admits, admits[1:])), "admission overtook an earlier request"
     for (n, lmax, _), (t, p, w), (tk, alm, cl) in zip(reqs[:2], inputs[:2], subs[:2]):
+        solo = lib.alm_from_points(t, p, w, lmax)
+        torch.cuda.synchronize()
+        assert torch.equal(alm, solo)
+
+
+def test_small_request_overtakes_large_ones(lib):
+    import torch
+    cats = [catalog(2_000_000, 95), catalog(2_000_000, 96), catalog(10_000, 97)]
+    lmaxes = (1024, 1024, 64)
+    ins = [(dev(t), dev(p), dev(w)) for t, p, w in cats]
+    torch.cuda.synchronize()
+    with lib.Server(arena_bytes=4 << 30, slots=2) as srv:
+        subs = [srv.submit(t, p, w, lmax) for (t, p, w), lmax in zip(ins, lmaxes)]
+        stats = [srv.wait(tk) for tk, _, _ in subs]
+    assert all(s.status == 0 for s in stats)
+    print("done after submission (s):", [round(s.done_s - s.submit_s, 4) for s in stats], flush=True)
+    assert stats[2].done_s < min(stats[0].done_s, stats[1].done_s), "the small request waited for the large ones"
+    for (tk, alm, cl), (t, p, w), lmax in zip(subs, ins, lmaxes):
         solo = lib.alm_from_points(t, p, w, lmax)
         torch.cuda.synchronize()
         assert torch.equal(alm, solo)

@@ -1,6 +1,8 @@
-"""Host-side checks of the request server: its arena and first-come-first-served
-admission (paper_2312_12285_amd/csrc/server_core.h) under a simulated executor,
-compiled with g++ and run on the CPU."""
+"""Host-side checks of the request server: its arena, memory admission (arrival
+order, passing until aged) and work-item schedule (chunks of point slices,
+shortest remaining work first, aged requests first; paper_2312_12285_amd/csrc/
+server_core.h) under a simulated executor, compiled with g++ under AddressSanitizer
+and UBSan and run on the CPU."""
 import os
 import subprocess
 
