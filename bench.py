@@ -765,6 +765,7 @@ def run_served(args):
                     last_note = time.monotonic()
                     print(f"[bench] {label}: completed {len(stats)}/{len(order)}", file=sys.stderr, flush=True)
         lat = np.array([stats[k].done_s - (start + arrivals[k]) for k in order])
+        slow = lat / (terms[order] / capacity_hint)       # latency over the request's time alone at capacity
         makespan = max(stats[k].done_s for k in order) - start
         tot = float(terms[order].sum())
         print(f"[bench] {label}: makespan {makespan:.1f} s, {tot / makespan:.3e} terms/s", file=sys.stderr, flush=True)
@@ -772,10 +773,15 @@ def run_served(args):
                 "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "makespan_s": round(makespan, 3),
                 "terms_per_s": tot / makespan,
                 "offered_terms_per_s": tot / max(1e-9, float(arrivals[order].max() - arrivals[order].min())),
-                "max_queue_wait_s": round(float(max(stats[k].admit_s - (start + arrivals[k]) for k in order)), 4)}
+                "max_queue_wait_s": round(float(max(stats[k].admit_s - (start + arrivals[k]) for k in order)), 4),
+                "p50_slowdown": round(float(np.percentile(slow, 50)), 2),
+                "p99_slowdown": round(float(np.percentile(slow, 99)), 2),
+                "p99_of_requests_above_1e12_terms_s": round(float(np.percentile(lat[terms[order] > 1e12], 99)), 4)
+                if (terms[order] > 1e12).any() else None}
 
     arrivals = np.array([r.arrival_s for r in reqs])
     order = list(range(K))
+    capacity_hint = 5.8e12          # FP64 terms/s of one device, for the slowdown figures only
     res = replay(arrivals, order, "trace at 50/s")
     capacity = res["terms_per_s"]
     offered = float(terms.sum() / arrivals.max())
@@ -840,7 +846,7 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--served-requests", type=int, default=500)
     ap.add_argument("--served-slots", type=int, default=4)
-    ap.add_argument("--served-arena-gb", type=float, default=4.0)
+    ap.add_argument("--served-arena-gb", type=float, default=16.0)
     ap.add_argument("--spline-error-table", action="store_true",
                     help="print the oracle's pointwise spline interpolation errors (CPU only) and exit")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -338,13 +338,13 @@ int ptalm_autotune(const double *theta, const double *phi, const double *w, int6
  * HIP streams.  A scheduler thread admits submitted requests into the arena
  * (their scratch footprint, ptalm_workspace_bytes of their call) in arrival
  * order, letting later requests that fit pass one that does not until it has
- * waited 2 s.  Each admitted request runs as work items: launches of its
+ * waited 30 s.  Each admitted request runs as work items: launches of its
  * transform over consecutive groups of its point slices (about 2e11 terms
  * each), then one finishing launch (the second pass and the spectrum).  Items
- * go to free slots, requests waiting longer than 2 s first (oldest first),
- * then the one with the least remaining work, so small requests do not wait
- * behind large ones; items of different requests run concurrently on the
- * device.  Each request uses the work plan of the same call made alone and
+ * go to free slots, the request with the least remaining work first, so small
+ * requests do not wait behind large ones; requests waiting longer than 30 s
+ * go before all others (oldest first), so none starves under overload; items
+ * of different requests run concurrently on the device.  Each request uses the work plan of the same call made alone and
  * its chunks compute exactly that call's slice partials, so its a_lm are
  * bitwise those of the solo call.
  * The catalog and output buffers are device memory owned by the caller: the

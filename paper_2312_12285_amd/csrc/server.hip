@@ -39,7 +39,7 @@ double now_s() {
 // terms of work per chunk aimed at (~35 ms of the whole device in FP64)
 constexpr double kChunkTerms = 2e11;
 // a request waiting longer than this (from submission) goes before shorter work
-constexpr double kAgeSeconds = 2.0;
+constexpr double kAgeSeconds = 30.0;
 
 struct Req {
     ptalm_request r;
