@@ -142,11 +142,17 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
         const bool first = (g == g_a);
         // ---- 1. point data; stage B = w Z (FP32) and x --------------------------
         const int64_t i = g * kG + tid;
-        double th = 1.5707963267948966, ph = 0.0;
         const bool valid = i < a.n;
-        if (valid) {
-            th = a.theta[i];
-            ph = a.phi[i];
+        // every load issued at once from a clamped index (the tail's points get
+        // weight 0 and a harmless position), so their latencies overlap
+        const int64_t ic = valid ? i : a.n - 1;
+        float wv[NW];
+#pragma unroll
+        for (int v = 0; v < NW; ++v) wv[v] = a.w32[(int64_t)v * a.n + ic];
+        double th = a.theta[ic], ph = a.phi[ic];
+        if (!valid) {
+            th = 1.5707963267948966;
+            ph = 0.0;
         }
         double st, ct, sp, cp;
         sincos(th, &st, &ct);
@@ -175,11 +181,11 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
             }
         }
         const float zr32 = (float)zr, zi32 = (float)zi;
-#pragma unroll 8
+#pragma unroll
         for (int v = 0; v < NW; ++v) {
-            const float wv = valid ? a.w32[(int64_t)v * a.n + i] : 0.f;
-            Bs[(2 * v) * kRowB + tid] = wv * zr32;
-            Bs[(2 * v + 1) * kRowB + tid] = wv * zi32;
+            const float wq = valid ? wv[v] : 0.f;
+            Bs[(2 * v) * kRowB + tid] = wq * zr32;
+            Bs[(2 * v + 1) * kRowB + tid] = wq * zi32;
         }
         Xs[tid] = (float)x;
         __syncthreads();
@@ -244,8 +250,7 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
             float prev[NOWN];
 #pragma unroll
             for (int o = 0; o < NOWN; ++o) {
-                const float v = pt[own_offset(o)];
-                prev[o] = first ? 0.f : v;
+                prev[o] = pt[own_offset(o)];
             }
             // step coefficients of the next tile (the tile after the last reads
             // the table's padding; steps past lmax-m land in padding rows)
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
 #pragma unroll
             for (int o = 0; o < NOWN; ++o) {
                 const float mine = half ? dv[NOWN + o] : dv[o];
-                pt[own_offset(o)] = prev[o] + (mine + xr[o * 64]);
+                pt[own_offset(o)] = (first ? 0.f : prev[o]) + (mine + xr[o * 64]);
             }
         }
     }
