@@ -122,164 +122,273 @@ __device__ inline void lds_barrier() {
 
 constexpr int kCB = 64;   // output block edge in i and in j
 constexpr int kSPitch = kCB + 2;
+constexpr int kCouplingThreads = 512;   // 4 matrix waves + 4 store waves
 constexpr size_t kCouplingLds = sizeof(double) * 4 * kCB * kSPitch;
 
-// Persistent kernel, one workgroup (4 waves) per CU: its LDS keeps a second
-// workgroup off the CU, so each wave has a SIMD's matrix core to itself.  The
-// workgroups take 64 x 64 blocks (i0.., j0..) of S_p from a counter, in order of
-// decreasing i0 - j0 (decreasing length of the k sum; both parities of a block
-// in turn), until none is left.  In a block the k range is split over the
-// waves in steps of 4; the four partial blocks go to LDS and are summed in wave
-// order while M is written.
-__global__ __launch_bounds__(256, 2) void coupling_mfma_kernel(const double *__restrict__ A,
-                                                               const double *__restrict__ B,
-                                                               const double *__restrict__ T, int lmax, int kw0,
-                                                               int kw1, int nblk, int *__restrict__ counter,
-                                                               double *__restrict__ M) {
-    // 4 partial blocks in dynamic LDS (kCouplingLds bytes): its size keeps a
-    // second workgroup off the CU, while the register budget is that of two
-    extern __shared__ double Sd[];
-    __shared__ int64_t unit_s;
-    const int64_t units = (int64_t)nblk * (nblk + 1);   // candidate blocks x 2 parities
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// The blocks of S_p (64 x 64 in (i, j) from (i0, j0) = 64 (ib, jb), one parity p)
+// that hold an entry of M, in the order the workgroups take them: decreasing
+// d = ib - jb (so decreasing length of the k sum), then increasing jb, the two
+// parities in turn.  A block holds one when its first entry has
+// l = i0 + j0 + p <= lmax, i.e. 2 jb + d <= L_p = floor((lmax - p) / 64); that is
+// floor((L_p - d) / 2) + 1 blocks for each d <= L_p, and
+// sum_{e = 0..E} (floor(e / 2) + 1) = floor(E^2 / 4) + E + 1 of them with d >= L_p - E.
+__device__ inline int64_t blocks_from(int L, int d) {   // blocks of one parity with d' >= d
+    if (d > L) return 0;
+    const int64_t E = L - d;
+    return E * E / 4 + E + 1;
+}
+
+struct CouplingBlock {
+    int i0, j0, p;
+};
+
+// The unit-th block of that order (0 <= unit < blocks_from(L0, 0) + blocks_from(L1, 0)).
+__device__ inline CouplingBlock coupling_block(int64_t unit, int L0, int L1) {
+    // the largest d whose predecessors (the blocks with d' > d) number at most unit
+    int lo = 0, hi = L0;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blocks_from(L0, mid) + blocks_from(L1, mid) <= unit)
+            hi = mid - 1;
+        else
+            lo = mid;
+    }
+    const int d = lo;
+    const int64_t r = unit - (blocks_from(L0, d + 1) + blocks_from(L1, d + 1));
+    const int jb = (int)(r >> 1), p = (int)(r & 1);
+    return {(jb + d) * kCB, jb * kCB, p};
+}
+
+// One matrix wave's share of block (i0, j0, p): the k steps k = j0 + 4 wave + lk + 16 s
+// (lk = lane / 16 picks one of four consecutive k, as the f64 MFMA's K = 4),
+// accumulated into the 4 x 4 tiles of 16 x 16 f64 results.  A step's operands
+// are windows of five sequences, each of which slides by one entry per step:
+//   a(i - k_s) for i = i0 + lr + 16 mt:   al[s - mt],  al[n] = A[i0 + lr - k - 16 n]
+//   b(i + k_s + p):                        be[s + mt],  be[n] = B[i0 + lr + k + p + 16 n]
+//   a(k_s - j) for j = j0 + lr + 16 nt:   ga[s - nt],  ga[n] = A[k - j0 - lr + 16 n]
+//   a(k_s + j + p):                        de[s + nt],  de[n] = A[k + j0 + lr + p + 16 n]
+//   (2 lambda + 1) W_lambda:               ta[s],       ta[n] = T[2 k + p + 32 n]
+// so a step loads one new entry of each, kDist steps ahead, into rings of kRing
+// registers indexed by n mod kRing; the loop is unrolled kRing times so that
+// every ring index is a constant.  The tables carry kTabPad zeros on both sides:
+// they make the terms with k > i, k < j, k + j + p > lmax or lambda > lmax_w
+// vanish without a test, and every index read here (at most kDist steps past a
+// wave's last step) stays inside them.
+__device__ inline void coupling_mma(const double *__restrict__ A, const double *__restrict__ B,
+                                    const double *__restrict__ T, int i0, int j0, int p, int ke, int wave, int lane,
+                                    v4d (&acc)[4][4]) {
+    constexpr int kDist = 2, kRing = kDist + 4;
     const int lr = lane & 15, lk = lane >> 4;
-    // thread 0 takes the next block number one block ahead, so that the
-    // atomic's latency is hidden behind the current block
-    int next = 0;
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    for (;;) {
-        if (threadIdx.x == 0) unit_s = next;
-        lds_barrier();
-        const int64_t u = unit_s;
-        if (u >= units) break;
-        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-        const int p = (int)(u & 1);
-        const int64_t t = u >> 1;
-        int q = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-        while ((int64_t)(q + 1) * (q + 2) / 2 <= t) ++q;
-        while ((int64_t)q * (q + 1) / 2 > t) --q;
-        const int jb = (int)(t - (int64_t)q * (q + 1) / 2);
-        const int ib = jb + (nblk - 1 - q);
-        const int i0 = ib * kCB, j0 = jb * kCB;
-        if (i0 + j0 > lmax - p) {   // no (i, j) with l = i + j + p <= lmax
-            lds_barrier();
-            continue;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int kw = j0 + 4 * wave;   // the wave's first k
+    const int nsteps = __builtin_amdgcn_readfirstlane(kw <= ke ? (ke - kw) / 16 + 1 : 0);
+    if (nsteps == 0) return;
+    const int k = kw + lk;
+    const double *pa = A + (i0 + lr - k);
+    const double *pb = B + (i0 + lr + k + p);
+    const double *pc = A + (k - j0 - lr);
+    const double *pd = A + (k + j0 + lr + p);
+    const double *pt = T + (2 * k + p);
+    double al[kRing], be[kRing], ga[kRing], de[kRing], ta[kRing];
+    // al and ga from n = -3, be and de from n = 0, up to what steps 0 .. kDist - 1 use
+#pragma unroll
+    for (int n = -3; n < kDist; ++n) {
+        al[(n + kRing) % kRing] = pa[-16 * n];
+        ga[(n + kRing) % kRing] = pc[16 * n];
+    }
+#pragma unroll
+    for (int n = 0; n < kDist + 3; ++n) {
+        be[n % kRing] = pb[16 * n];
+        de[n % kRing] = pd[16 * n];
+    }
+#pragma unroll
+    for (int n = 0; n < kDist; ++n) ta[n] = pt[32 * n];
+    // step s = s0 + r at ring phase r; the pointers stand at step s0, so every offset is a constant
+    auto step = [&](int r) {
+        const int n = r + kDist;
+        al[(r + kDist) % kRing] = pa[-16 * n];
+        ga[(r + kDist) % kRing] = pc[16 * n];
+        be[(r + kDist + 3) % kRing] = pb[16 * (n + 3)];
+        de[(r + kDist + 3) % kRing] = pd[16 * (n + 3)];
+        ta[(r + kDist) % kRing] = pt[32 * n];
+        double h[4], g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            h[u] = al[(r - u + kRing) % kRing] * be[(r + u) % kRing] * ta[r];
+            g[u] = ga[(r - u + kRing) % kRing] * de[(r + u) % kRing];
         }
-        const int kw = p ? kw1 : kw0;
-        const int ke = min(min(i0 + kCB - 1, lmax - p - j0), kw);
-
-        v4d acc[4][4];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
-
-        // Operands of one k step (four consecutive k across the lane groups, 64 rows
-        // i and 64 columns j).  The tables carry kTabPad zeros on both sides, which
-        // make the terms with k > i or k < j vanish without a test, and every index
-        // below stays within the padding for k <= ke + 3.  Two register sets
-        // alternate so that the loads of one step are in flight during the matrix
-        // products of the previous one.
-        int k = j0 + 4 * wave + lk;
-        const double *pa = A + (i0 + lr - k);       // a(i - k),      i = i0 + 16 mt + lr
-        const double *pb = B + (i0 + lr + k + p);   // b(i + k + p)
-        const double *pt = T + (2 * k + p);         // (2 lambda + 1) W_lambda
-        const double *pc = A + (k - j0 - lr);       // a(k - j),      j = j0 + 16 nt + lr
-        const double *pd = A + (k + j0 + lr + p);   // a(k + j + p)
-        struct Ops {
-            double a[4], b[4], c[4], d[4], t;
-        };
-        auto load = [&](Ops &o) {
-            o.t = pt[0];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                o.a[u] = pa[16 * u];
-                o.b[u] = pb[16 * u];
-                o.c[u] = pc[-16 * u];
-                o.d[u] = pd[16 * u];
-            }
-            pa -= 16;
-            pb += 16;
-            pt += 32;
-            pc += 16;
-            pd += 16;
-        };
-        auto mma = [&](const Ops &o) {
-            double h[4], g[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                h[u] = o.a[u] * o.b[u] * o.t;
-                g[u] = o.c[u] * o.d[u];
-            }
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[mt], g[nt], acc[mt][nt], 0, 0, 0);
-        };
-        const int kw0_ = j0 + 4 * wave;
-        const int nsteps = kw0_ <= ke ? (ke - kw0_) / 16 + 1 : 0;   // this wave's k steps
-        Ops X, Y;
-        if (nsteps > 0) load(X);
-        int st = 0;
-        for (; st + 2 <= nsteps; st += 2) {
-            load(Y);
-            mma(X);
-            if (st + 2 < nsteps) load(X);
-            mma(Y);
-        }
-        if (st < nsteps) mma(X);
-
-        // partial blocks to LDS (16x16 f64 result: register r of a lane holds row
-        // lane / 16 + 4 r, column lane % 16)
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[mt], g[nt], acc[mt][nt], 0, 0, 0);
+    };
+    int s0 = 0;
+    for (; s0 + kRing <= nsteps; s0 += kRing) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    Sd[(wave * kCB + 16 * mt + lk + 4 * r) * kSPitch + 16 * nt + lr] = acc[mt][nt][r];
-        lds_barrier();
-        // the block: sum of the four partials in wave order, into partial 0
+        for (int r = 0; r < kRing; ++r) step(r);
+        pa -= 16 * kRing;
+        pc += 16 * kRing;
+        pb += 16 * kRing;
+        pd += 16 * kRing;
+        pt += 32 * kRing;
+    }
 #pragma unroll
-        for (int e = threadIdx.x; e < kCB * kCB; e += 256) {
-            double *x = Sd + (e >> 6) * kSPitch + (e & 63);
-            constexpr int w = kCB * kSPitch;
-            x[0] = ((x[0] + x[w]) + x[2 * w]) + x[3 * w];
-        }
-        lds_barrier();
+    for (int r = 0; r < kRing - 1; ++r)
+        if (s0 + r < nsteps) step(r);
+}
 
-        const int64_t n1 = lmax + 1;
-        // M is written once and not read here: streaming stores keep the tables in the caches.
-        // M[l][l'] (l >= l'): rows sigma = i + j of the block, one lane per i
-#pragma unroll 4
-        for (int it = 0; it < kCB / 2; ++it) {
-            const int rs = wave + 4 * it;
-            const int sigma = i0 + j0 + rs;
-            const int l = sigma + p;
-            const int i = max(i0, sigma - (j0 + kCB - 1)) + lane;
-            const int j = sigma - i;
-            if (rs < 2 * kCB - 1 && l <= lmax && i <= min(i0 + kCB - 1, sigma - j0) && i >= j) {
-                const int lp = i - j;
-                const double v = (2.0 * lp + 1.0) * kInv4Pi * Sd[(i - i0) * kSPitch + j - j0];
-                __builtin_nontemporal_store(v, M + l * n1 + lp);
-            }
+// Writes one block of S_p (P0 + P1 in LDS, 64 x 64 in (i, j) from (i0, j0)) to both
+// triangles of M, scaled by (2l'+1)/(4 pi) resp. (2l+1)/(4 pi); store wave sw
+// takes every fourth row of each.  A row of M meets the block along a diagonal
+// of (i, j), so a block writes every other entry of up to 64 x 2 in each row.
+// Eight rows are read from LDS before any of them is stored (the empty asm
+// statement keeps the compiler from moving the reads under the store
+// conditions).  M is written once and not read here: streaming stores keep the
+// tables in the caches.
+__device__ inline void store_block(const double *__restrict__ P0, const double *__restrict__ P1, int i0, int j0,
+                                   int p, int sw, int lane, int lmax, double *__restrict__ M) {
+    const int64_t n1 = lmax + 1;
+    const int dij = i0 - j0;
+    // M[l][l'] (l >= l'): row rs = i + j - i0 - j0 of the block, one lane per i;
+    // rs < 64: i - i0 = lane, j - j0 = rs - lane; rs >= 64: i - i0 = rs - 63 + lane, j - j0 = 63 - lane
+#pragma unroll 1
+    for (int it0 = 0; it0 < kCB / 2; it0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int rs = sw + 4 * (it0 + u);
+            const int x = rs < kCB ? (kCB + 1) * lane + rs : kSPitch * (rs - (kCB - 1)) + (kCB + 1) * lane + (kCB - 1);
+            const int xc = x < kCB * kSPitch ? x : 0;
+            v[u] = P0[xc] + P1[xc];
         }
-        // M[l'][l] (l > l'): rows tau = i - j of the block, one lane per j
-#pragma unroll 4
-        for (int it = 0; it < kCB / 2; ++it) {
-            const int rt = wave + 4 * it;
-            const int tau = i0 - j0 - (kCB - 1) + rt;
-            const int j = max(j0, i0 - tau) + lane;
-            const int i = tau + j;
-            const int l = i + j + p;
-            if (rt < 2 * kCB - 1 && tau >= 0 && j <= min(j0 + kCB - 1, i0 + kCB - 1 - tau) && l <= lmax &&
-                (j > 0 || p > 0)) {
-                const double v = (2.0 * l + 1.0) * kInv4Pi * Sd[(i - i0) * kSPitch + j - j0];
-                __builtin_nontemporal_store(v, M + tau * n1 + l);
-            }
+        asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int rs = sw + 4 * (it0 + u);
+            const int l = i0 + j0 + rs + p;
+            const int lp = rs < kCB ? dij + 2 * lane - rs : dij + rs - 2 * (kCB - 1) + 2 * lane;   // i - j
+            const bool in_block = rs < kCB ? lane <= rs : lane <= 2 * (kCB - 1) - rs;
+            if (rs < 2 * kCB - 1 && l <= lmax && in_block && lp >= 0)
+                __builtin_nontemporal_store((2.0 * lp + 1.0) * kInv4Pi * v[u], M + l * n1 + lp);
         }
-        lds_barrier();   // S and unit_s are reused by the next block
+    }
+    // M[l'][l] (l > l'): row rt = i - j - (i0 - j0) + 63 of the block, one lane per j;
+    // rt < 64: j - j0 = 63 - rt + lane, i - i0 = lane; rt >= 64: j - j0 = lane, i - i0 = rt - 63 + lane
+#pragma unroll 1
+    for (int it0 = 0; it0 < kCB / 2; it0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int rt = sw + 4 * (it0 + u);
+            const int x = rt < kCB ? kSPitch * lane + (kCB - 1) - rt + lane : kSPitch * (rt - (kCB - 1) + lane) + lane;
+            const int xc = x < kCB * kSPitch ? x : 0;
+            v[u] = P0[xc] + P1[xc];
+        }
+        asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int rt = sw + 4 * (it0 + u);
+            const int tau = dij - (kCB - 1) + rt;
+            const int jj = rt < kCB ? (kCB - 1) - rt + lane : lane;
+            const int l = 2 * (j0 + jj) + tau + p;   // i + j + p with i = tau + j
+            const bool in_block = rt < kCB ? lane <= rt : lane <= 2 * (kCB - 1) - rt;
+            if (rt < 2 * kCB - 1 && tau >= 0 && in_block && l <= lmax && (j0 + jj > 0 || p > 0))
+                __builtin_nontemporal_store((2.0 * l + 1.0) * kInv4Pi * v[u], M + tau * n1 + l);
+        }
+    }
+}
+
+// Persistent kernel, one workgroup per CU (its LDS keeps a second one off the
+// CU).  Waves 0-3 run the matrix products: each has a SIMD's matrix core to
+// itself and takes a quarter of the k steps of the current block.  Waves 4-7
+// write the previous block to M meanwhile (at a raised issue priority, as the
+// matrix waves would otherwise take nearly every issue slot), so that the
+// stores overlap the matrix work instead of following it.  The four partial
+// blocks are summed in LDS as (w0 + w2) + (w1 + w3): waves 2 and 3 hand theirs
+// to waves 0 and 1 through buffers P0 and P1, which then hold the two sums; two
+// such buffer pairs alternate between consecutive blocks.
+__global__ __launch_bounds__(kCouplingThreads, 1) void coupling_mfma_kernel(const double *__restrict__ A,
+                                                                           const double *__restrict__ B,
+                                                                           const double *__restrict__ T, int lmax,
+                                                                           int kw0, int kw1,
+                                                                           int *__restrict__ counter,
+                                                                           double *__restrict__ M) {
+    extern __shared__ double Sd[];   // [2 buffer pairs][P0, P1][kCB][kSPitch], kCouplingLds bytes
+    __shared__ int64_t unit_s;
+    constexpr int kBuf = 2 * kCB * kSPitch;
+    const int L0 = lmax / kCB, L1 = lmax >= 1 ? (lmax - 1) / kCB : -1;
+    const int64_t units = blocks_from(L0, 0) + blocks_from(L1, 0);
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lr = lane & 15, lk = lane >> 4;
+    // thread 0 takes block numbers one block ahead, so that the atomic's latency
+    // is hidden behind the current block
+    int next = 0;
+    if (threadIdx.x == 0) {
+        unit_s = atomicAdd(counter, 1);
+        next = atomicAdd(counter, 1);
+    }
+    lds_barrier();
+    int64_t u = unit_s;
+    if (wave >= 4) __builtin_amdgcn_s_setprio(3);
+    bool pending = false;   // the previous block waits in buffer pair (n - 1) & 1
+    CouplingBlock prev{0, 0, 0};
+    for (int n = 0;; ++n) {
+        if (u >= units && !pending) break;
+        const bool have = u < units;
+        const CouplingBlock cb = have ? coupling_block(u, L0, L1) : CouplingBlock{0, 0, 0};
+        double *Q = Sd + (n & 1) * kBuf;
+        if (wave < 4) {
+            if (have) {
+                const int kw = cb.p ? kw1 : kw0;
+                const int ke = min(min(cb.i0 + kCB - 1, lmax - cb.p - cb.j0), kw);
+                v4d acc[4][4];
+                coupling_mma(A, B, T, cb.i0, cb.j0, cb.p, ke, wave, lane, acc);
+                // (16x16 f64 result tile: register r of a lane holds row lane / 16 + 4 r, column lane % 16)
+                if (wave >= 2) {
+                    double *P = Q + (wave - 2) * (kCB * kSPitch);
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                P[(16 * mt + lk + 4 * r) * kSPitch + 16 * nt + lr] = acc[mt][nt][r];
+                }
+                lds_barrier();
+                if (wave < 2) {
+                    double *P = Q + wave * (kCB * kSPitch);
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                double *x = P + (16 * mt + lk + 4 * r) * kSPitch + 16 * nt + lr;
+                                *x = acc[mt][nt][r] + *x;
+                            }
+                }
+            } else {
+                lds_barrier();
+            }
+            if (threadIdx.x == 0) {
+                unit_s = next;
+                next = atomicAdd(counter, 1);
+            }
+        } else {
+            if (pending) {
+                const double *P0 = Sd + ((n - 1) & 1) * kBuf;
+                store_block(P0, P0 + kCB * kSPitch, prev.i0, prev.j0, prev.p, wave - 4, lane, lmax, M);
+            }
+            lds_barrier();
+        }
+        lds_barrier();   // the block's sums are in Q; unit_s holds the next block
+        pending = have;
+        prev = cb;
+        u = unit_s;
     }
 }
 
@@ -564,14 +673,12 @@ hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, dou
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const int lw = lmax_w < 2 * lmax ? lmax_w : 2 * lmax;
     const int kw0 = lw >> 1, kw1 = lw >= 1 ? (lw - 1) >> 1 : -1;
-    const int nblk = (lmax + kCB) / kCB;
-    const int64_t units = (int64_t)nblk * (nblk + 1);
-    const unsigned grid = (unsigned)(units < cus ? units : (cus > 0 ? cus : 1));
+    const unsigned grid = (unsigned)(cus > 0 ? cus : 1);
     if ((e = hipFuncSetAttribute((const void *)coupling_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kCouplingLds)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(coupling_mfma_kernel, dim3(grid), dim3(256), kCouplingLds, stream, (const double *)A, (const double *)B,
-                       (const double *)T, lmax, kw0, kw1, nblk, counter, M);
+    hipLaunchKernelGGL(coupling_mfma_kernel, dim3(grid), dim3(kCouplingThreads), kCouplingLds, stream,
+                       (const double *)A, (const double *)B, (const double *)T, lmax, kw0, kw1, counter, M);
     return hipGetLastError();
 }
 
