@@ -48,11 +48,30 @@ __device__ inline dd dd_mul(dd x, dd y) {
     return {s, e - (s - p)};
 }
 
-// (2n-1)/(2n) as a double-double (the remainder of the division is exact)
+// 1/d for d > 0 to about half an ulp: the hardware reciprocal and one Newton step
+// (an IEEE division is several times as many instructions)
+__device__ inline double recip(double d) {
+    double x = __builtin_amdgcn_rcp(d);
+    x = fma(x, fma(-d, x, 1.0), x);
+    return fma(x, fma(-d, x, 1.0), x);
+}
+
+// (2n-1)/(2n) as a double-double: q plus the exact remainder of num - q den, divided by den
 __device__ inline dd odd_even_ratio(int n) {
     const double num = 2.0 * n - 1.0, den = 2.0 * n;
-    const double q = num / den;
-    return {q, fma(-q, den, num) / den};
+    const double inv = recip(den);
+    const double q = num * inv;
+    return {q, fma(-q, den, num) * inv};
+}
+
+// inclusive product scan of a double-double over the 64 lanes of a wave
+__device__ inline dd wave_scan_mul(dd v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double h = __shfl_up(v.hi, off), l = __shfl_up(v.lo, off);
+        if (lane >= off) v = dd_mul(dd{h, l}, v);
+    }
+    return v;
 }
 
 constexpr int kTabThreads = 1024;
@@ -63,16 +82,18 @@ constexpr int kTabPad = 128;   // zeros on either side of each coupling table
 //   B[J] = 1 / ((2J+1) a(J))                      J in [0, 2 lmax]
 //   T[lambda] = (2 lambda + 1)(W_lambda - shot)   lambda in [0, 2 lmax + 1], 0 beyond lmax_w
 // (A, B and T point at entry 0).  a(n) is a prefix product, taken in
-// double-double: each thread multiplies its chunk of factors, a Hillis-Steele
-// scan over the workgroup gives each chunk its starting value.
+// double-double: each thread multiplies its chunk of factors; a scan within each
+// wave (lane shuffles) and one over the 16 wave totals (through LDS, one barrier)
+// give each chunk its starting value.
 __global__ __launch_bounds__(kTabThreads) void coupling_tables_kernel(const double *__restrict__ Wl, int lmax_w,
                                                                       const double *__restrict__ shot, int lmax,
                                                                       double *__restrict__ A, double *__restrict__ B,
                                                                       double *__restrict__ T,
                                                                       int *__restrict__ counter) {
-    __shared__ double sh[kTabThreads], sl[kTabThreads];
-    const int tid = threadIdx.x;
-    if (tid == 0) *counter = 0;   // block counter of coupling_mfma_kernel
+    constexpr int kWaves = kTabThreads / 64;
+    __shared__ double wh[kWaves], wl[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) *counter = 0;   // unit counter of coupling_mfma_kernel
     const int N = 2 * lmax + 1;
     for (int e = tid; e < kTabPad; e += kTabThreads) {
         A[e - kTabPad] = 0.0;
@@ -82,34 +103,32 @@ __global__ __launch_bounds__(kTabThreads) void coupling_tables_kernel(const doub
         T[e - kTabPad] = 0.0;
         T[N + 1 + e] = 0.0;
     }
+    const double sub = shot ? shot[0] : 0.0;
+    for (int lam = tid; lam <= N; lam += kTabThreads) T[lam] = lam <= lmax_w ? (2.0 * lam + 1.0) * (Wl[lam] - sub) : 0.0;
     const int chunk = (N + kTabThreads - 1) / kTabThreads;
     const int n_lo = tid * chunk < N ? tid * chunk : N;
     const int n_hi = n_lo + chunk < N ? n_lo + chunk : N;
     dd P = {1.0, 0.0};
     for (int n = n_lo > 1 ? n_lo : 1; n < n_hi; ++n) P = dd_mul(P, odd_even_ratio(n));
-    sh[tid] = P.hi;
-    sl[tid] = P.lo;
-    __syncthreads();
-    for (int off = 1; off < kTabThreads; off <<= 1) {
-        dd v = {sh[tid], sl[tid]};
-        if (tid >= off) v = dd_mul(dd{sh[tid - off], sl[tid - off]}, v);
-        __syncthreads();
-        sh[tid] = v.hi;
-        sl[tid] = v.lo;
-        __syncthreads();
+    const dd inc = wave_scan_mul(P, lane);   // product of the chunks of lanes 0..lane of this wave
+    if (lane == 63) {
+        wh[wave] = inc.hi;
+        wl[wave] = inc.lo;
     }
-    dd r = tid > 0 ? dd{sh[tid - 1], sl[tid - 1]} : dd{1.0, 0.0};
+    __syncthreads();
+    dd r = {1.0, 0.0};   // product of all chunks before this thread's
+    for (int w = 0; w < wave; ++w) r = dd_mul(r, dd{wh[w], wl[w]});
+    const dd prev = {__shfl_up(inc.hi, 1), __shfl_up(inc.lo, 1)};
+    if (lane > 0) r = dd_mul(r, prev);
     for (int n = n_lo; n < n_hi; ++n) {
         if (n >= 1) r = dd_mul(r, odd_even_ratio(n));
         if (n <= lmax) A[n] = r.hi;
         const double c = 2.0 * n + 1.0;
         const double dh = r.hi * c;
         const double dl = fma(r.hi, c, -dh) + r.lo * c;
-        const double q = 1.0 / dh;
+        const double q = recip(dh);
         B[n] = fma(q, fma(-q, dh, 1.0) - q * dl, q);
     }
-    const double sub = shot ? shot[0] : 0.0;
-    for (int lam = tid; lam <= N; lam += kTabThreads) T[lam] = lam <= lmax_w ? (2.0 * lam + 1.0) * (Wl[lam] - sub) : 0.0;
 }
 
 // Workgroup barrier that orders LDS accesses only: global stores still in
@@ -120,212 +139,225 @@ __device__ inline void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-constexpr int kCB = 64;   // output block edge in i and in j
-constexpr int kSPitch = kCB + 2;
-constexpr int kCouplingThreads = 512;   // 4 matrix waves + 4 store waves
-constexpr size_t kCouplingLds = sizeof(double) * 4 * kCB * kSPitch;
+constexpr int kCI = 64;                     // unit edge in i
+constexpr int kCJ = 32;                     // unit edge in j
+constexpr int kPitch = kCJ + 2;             // LDS row pitch of a partial tile (doubles)
+constexpr int kTile = kCI * kPitch;         // one parity's 64 x 32 tile
+constexpr int kCouplingThreads = 512;       // 4 matrix waves + 4 store waves
+constexpr size_t kCouplingLds = sizeof(double) * 2 * 2 * 2 * kTile;   // [buffer pair][P0, P1][parity]
 
-// The blocks of S_p (64 x 64 in (i, j) from (i0, j0) = 64 (ib, jb), one parity p)
-// that hold an entry of M, in the order the workgroups take them: decreasing
-// d = ib - jb (so decreasing length of the k sum), then increasing jb, the two
-// parities in turn.  A block holds one when its first entry has
-// l = i0 + j0 + p <= lmax, i.e. 2 jb + d <= L_p = floor((lmax - p) / 64); that is
-// floor((L_p - d) / 2) + 1 blocks for each d <= L_p, and
-// sum_{e = 0..E} (floor(e / 2) + 1) = floor(E^2 / 4) + E + 1 of them with d >= L_p - E.
-__device__ inline int64_t blocks_from(int L, int d) {   // blocks of one parity with d' >= d
+// Work units: the 64 x 32 blocks (i0, j0) = (64 ib, 64 jb + 32 h) of S_0 and S_1
+// together (both parities, h the half of a 64-wide column block) that hold an
+// entry of M, in the order the workgroups take them: decreasing d = ib - jb (so
+// decreasing length of the k sum), then increasing jb, the two halves in turn.
+// A unit holds one when its first entry has l = i0 + j0 <= lmax, i.e.
+// 2 jb + d <= L_h = floor((lmax - 32 h) / 64); that is floor((L_h - d) / 2) + 1
+// units for each d <= L_h, and sum_{e = 0..E} (floor(e / 2) + 1) =
+// floor(E^2 / 4) + E + 1 of them with d >= L_h - E.
+__device__ inline int64_t units_from(int L, int d) {   // units of one half with d' >= d
     if (d > L) return 0;
     const int64_t E = L - d;
     return E * E / 4 + E + 1;
 }
 
-struct CouplingBlock {
-    int i0, j0, p;
+struct CouplingUnit {
+    int i0, j0;
 };
 
-// The unit-th block of that order (0 <= unit < blocks_from(L0, 0) + blocks_from(L1, 0)).
-__device__ inline CouplingBlock coupling_block(int64_t unit, int L0, int L1) {
-    // the largest d whose predecessors (the blocks with d' > d) number at most unit
+// The unit-th unit of that order (0 <= unit < units_from(L0, 0) + units_from(L1, 0)).
+__device__ inline CouplingUnit coupling_unit(int64_t unit, int L0, int L1) {
+    // the largest d whose predecessors (the units with d' > d) number at most unit
     int lo = 0, hi = L0;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (blocks_from(L0, mid) + blocks_from(L1, mid) <= unit)
+        if (units_from(L0, mid) + units_from(L1, mid) <= unit)
             hi = mid - 1;
         else
             lo = mid;
     }
     const int d = lo;
-    const int64_t r = unit - (blocks_from(L0, d + 1) + blocks_from(L1, d + 1));
-    const int jb = (int)(r >> 1), p = (int)(r & 1);
-    return {(jb + d) * kCB, jb * kCB, p};
+    const int64_t r = unit - (units_from(L0, d + 1) + units_from(L1, d + 1));
+    const int jb = (int)(r >> 1), h = (int)(r & 1);
+    return {(jb + d) * 2 * kCJ, jb * 2 * kCJ + h * kCJ};
 }
 
-// One matrix wave's share of block (i0, j0, p): the k steps k = j0 + 4 wave + lk + 16 s
-// (lk = lane / 16 picks one of four consecutive k, as the f64 MFMA's K = 4),
-// accumulated into the 4 x 4 tiles of 16 x 16 f64 results.  A step's operands
-// are windows of five sequences, each of which slides by one entry per step:
+// two adjacent table entries (p = 0 and p = 1), 8-byte aligned
+struct Pair {
+    double v[2];
+};
+__device__ inline Pair ld_pair(const double *p) { return Pair{{p[0], p[1]}}; }
+
+// One matrix wave's share of unit (i0, j0): the k steps k = j0 + 4 wave + lk + 16 s
+// (lk = lane / 16 picks one of four consecutive k, as the f64 MFMA's K = 4) for
+// both parities, into 2 x 4 x 2 tiles of 16 x 16 f64 results.  A step's operands
+// H_p[i][k] = a(i - k) b(i + k + p) and K_p[j][k] T(2k + p) = a(k - j) a(k + j + p) T(2k + p)
+// are formed from windows of five sequences, each sliding by one entry per step:
 //   a(i - k_s) for i = i0 + lr + 16 mt:   al[s - mt],  al[n] = A[i0 + lr - k - 16 n]
-//   b(i + k_s + p):                        be[s + mt],  be[n] = B[i0 + lr + k + p + 16 n]
+//   b(i + k_s + p):                        be[s + mt],  be[n] = B[i0 + lr + k + 16 n + p]
 //   a(k_s - j) for j = j0 + lr + 16 nt:   ga[s - nt],  ga[n] = A[k - j0 - lr + 16 n]
-//   a(k_s + j + p):                        de[s + nt],  de[n] = A[k + j0 + lr + p + 16 n]
-//   (2 lambda + 1) W_lambda:               ta[s],       ta[n] = T[2 k + p + 32 n]
-// so a step loads one new entry of each, kDist steps ahead, into rings of kRing
-// registers indexed by n mod kRing; the loop is unrolled kRing times so that
-// every ring index is a constant.  The tables carry kTabPad zeros on both sides:
-// they make the terms with k > i, k < j, k + j + p > lmax or lambda > lmax_w
-// vanish without a test, and every index read here (at most kDist steps past a
-// wave's last step) stays inside them.
+//   a(k_s + j + p):                        de[s + nt],  de[n] = A[k + j0 + lr + 16 n + p]
+//   (2 lambda + 1) W_lambda:               ta[s],       ta[n] = T[2 k + 32 n + p]
+// (be, de and ta hold both parities, two adjacent table entries), so a step loads
+// one new entry of each, one step ahead, into register rings indexed by n mod
+// their length (6, 6, 3, 3, 2); the loop is unrolled 6 times so that every ring
+// index is a constant.  The tables carry kTabPad zeros on both sides: they make
+// the terms with k > i, k < j, k + j + p > lmax or lambda > lmax_w vanish without
+// a test, and every index read here (at most a step past the wave's last step)
+// stays inside them.
 __device__ inline void coupling_mma(const double *__restrict__ A, const double *__restrict__ B,
-                                    const double *__restrict__ T, int i0, int j0, int p, int ke, int wave, int lane,
-                                    v4d (&acc)[4][4]) {
-    constexpr int kDist = 2, kRing = kDist + 4;
+                                    const double *__restrict__ T, int i0, int j0, int ke, int wave, int lane,
+                                    v4d (&acc)[2][4][2]) {
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[p][mt][nt] = v4d{0.0, 0.0, 0.0, 0.0};
     const int kw = j0 + 4 * wave;   // the wave's first k
     const int nsteps = __builtin_amdgcn_readfirstlane(kw <= ke ? (ke - kw) / 16 + 1 : 0);
     if (nsteps == 0) return;
     const int k = kw + lk;
     const double *pa = A + (i0 + lr - k);
-    const double *pb = B + (i0 + lr + k + p);
+    const double *pb = B + (i0 + lr + k);
     const double *pc = A + (k - j0 - lr);
-    const double *pd = A + (k + j0 + lr + p);
-    const double *pt = T + (2 * k + p);
-    double al[kRing], be[kRing], ga[kRing], de[kRing], ta[kRing];
-    // al and ga from n = -3, be and de from n = 0, up to what steps 0 .. kDist - 1 use
+    const double *pd = A + (k + j0 + lr);
+    const double *pt = T + 2 * k;
+    double al[6], ga[3];
+    Pair be[6], de[3], ta[2];
 #pragma unroll
-    for (int n = -3; n < kDist; ++n) {
-        al[(n + kRing) % kRing] = pa[-16 * n];
-        ga[(n + kRing) % kRing] = pc[16 * n];
-    }
+    for (int n = -3; n <= 0; ++n) al[(n + 6) % 6] = pa[-16 * n];
 #pragma unroll
-    for (int n = 0; n < kDist + 3; ++n) {
-        be[n % kRing] = pb[16 * n];
-        de[n % kRing] = pd[16 * n];
-    }
+    for (int n = 0; n <= 3; ++n) be[n] = ld_pair(pb + 16 * n);
 #pragma unroll
-    for (int n = 0; n < kDist; ++n) ta[n] = pt[32 * n];
-    // step s = s0 + r at ring phase r; the pointers stand at step s0, so every offset is a constant
+    for (int n = -1; n <= 0; ++n) ga[(n + 3) % 3] = pc[16 * n];
+#pragma unroll
+    for (int n = 0; n <= 1; ++n) de[n] = ld_pair(pd + 16 * n);
+    ta[0] = ld_pair(pt);
+    // step s = s0 + r (r = s mod 6); the pointers stand at step s0, so every offset is a constant
     auto step = [&](int r) {
-        const int n = r + kDist;
-        al[(r + kDist) % kRing] = pa[-16 * n];
-        ga[(r + kDist) % kRing] = pc[16 * n];
-        be[(r + kDist + 3) % kRing] = pb[16 * (n + 3)];
-        de[(r + kDist + 3) % kRing] = pd[16 * (n + 3)];
-        ta[(r + kDist) % kRing] = pt[32 * n];
-        double h[4], g[4];
+        al[(r + 1) % 6] = pa[-16 * (r + 1)];
+        be[(r + 4) % 6] = ld_pair(pb + 16 * (r + 4));
+        ga[(r + 1) % 3] = pc[16 * (r + 1)];
+        de[(r + 2) % 3] = ld_pair(pd + 16 * (r + 2));
+        ta[(r + 1) % 2] = ld_pair(pt + 32 * (r + 1));
+        double h[2][4], g[2][2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            h[u] = al[(r - u + kRing) % kRing] * be[(r + u) % kRing] * ta[r];
-            g[u] = ga[(r - u + kRing) % kRing] * de[(r + u) % kRing];
+        for (int p = 0; p < 2; ++p) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) h[p][mt] = al[(r - mt + 6) % 6] * be[(r + mt) % 6].v[p];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) g[p][nt] = ga[(r - nt + 3) % 3] * de[(r + nt) % 3].v[p] * ta[r % 2].v[p];
         }
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[mt], g[nt], acc[mt][nt], 0, 0, 0);
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[p][mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[p][mt], g[p][nt], acc[p][mt][nt], 0, 0, 0);
     };
     int s0 = 0;
-    for (; s0 + kRing <= nsteps; s0 += kRing) {
+    for (; s0 + 6 <= nsteps; s0 += 6) {
 #pragma unroll
-        for (int r = 0; r < kRing; ++r) step(r);
-        pa -= 16 * kRing;
-        pc += 16 * kRing;
-        pb += 16 * kRing;
-        pd += 16 * kRing;
-        pt += 32 * kRing;
+        for (int r = 0; r < 6; ++r) step(r);
+        pa -= 16 * 6;
+        pb += 16 * 6;
+        pc += 16 * 6;
+        pd += 16 * 6;
+        pt += 32 * 6;
     }
 #pragma unroll
-    for (int r = 0; r < kRing - 1; ++r)
+    for (int r = 0; r < 5; ++r)
         if (s0 + r < nsteps) step(r);
 }
 
-// Writes one block of S_p (P0 + P1 in LDS, 64 x 64 in (i, j) from (i0, j0)) to both
-// triangles of M, scaled by (2l'+1)/(4 pi) resp. (2l+1)/(4 pi); store wave sw
-// takes every fourth row of each.  A row of M meets the block along a diagonal
-// of (i, j), so a block writes every other entry of up to 64 x 2 in each row.
-// Eight rows are read from LDS before any of them is stored (the empty asm
-// statement keeps the compiler from moving the reads under the store
-// conditions).  M is written once and not read here: streaming stores keep the
-// tables in the caches.
-__device__ inline void store_block(const double *__restrict__ P0, const double *__restrict__ P1, int i0, int j0,
-                                   int p, int sw, int lane, int lmax, double *__restrict__ M) {
+// Writes unit (i0, j0) (the sums P0 + P1 in LDS, one 64 x 32 tile per parity) to
+// both triangles of M, scaled by (2l'+1)/(4 pi) resp. (2l+1)/(4 pi); store wave sw
+// takes every fourth row of each.  In a row of M the two parities alternate, so
+// a row of the unit is one run of up to 64 consecutive entries: one store
+// instruction of whole lines.  Eight rows are read from LDS before any of them is
+// stored (the empty asm statement keeps the compiler from moving the reads under
+// the store conditions).  M is written once and not read here: streaming stores
+// keep the tables in the caches.
+__device__ inline void store_unit(const double *__restrict__ P0, const double *__restrict__ P1, int i0, int j0,
+                                  int sw, int lane, int lmax, double *__restrict__ M) {
     const int64_t n1 = lmax + 1;
     const int dij = i0 - j0;
-    // M[l][l'] (l >= l'): row rs = i + j - i0 - j0 of the block, one lane per i;
-    // rs < 64: i - i0 = lane, j - j0 = rs - lane; rs >= 64: i - i0 = rs - 63 + lane, j - j0 = 63 - lane
+    // M[l][l'] (l >= l'): row sig = l - i0 - j0 in [0, 95]; lane at c = l' - (i0 - j0);
+    // p = parity of sig + c, i - i0 = (sig - p + c) / 2, j - j0 = (sig - p - c) / 2
 #pragma unroll 1
-    for (int it0 = 0; it0 < kCB / 2; it0 += 8) {
+    for (int it0 = 0; it0 < 24; it0 += 8) {
         double v[8];
+        bool ok[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int rs = sw + 4 * (it0 + u);
-            const int x = rs < kCB ? (kCB + 1) * lane + rs : kSPitch * (rs - (kCB - 1)) + (kCB + 1) * lane + (kCB - 1);
-            const int xc = x < kCB * kSPitch ? x : 0;
-            v[u] = P0[xc] + P1[xc];
+            const int sig = sw + 4 * (it0 + u);
+            const int c = max(sig - (kCI - 1), -sig) + lane;
+            const int p = (sig + c) & 1;
+            const int ii = (sig - p + c) >> 1, jj = (sig - p - c) >> 1;
+            ok[u] = ii >= 0 && ii < kCI && jj >= 0 && jj < kCJ && dij + c >= 0 && i0 + j0 + sig <= lmax;
+            const int x = ok[u] ? p * kTile + ii * kPitch + jj : 0;
+            v[u] = P0[x] + P1[x];
         }
         asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int rs = sw + 4 * (it0 + u);
-            const int l = i0 + j0 + rs + p;
-            const int lp = rs < kCB ? dij + 2 * lane - rs : dij + rs - 2 * (kCB - 1) + 2 * lane;   // i - j
-            const bool in_block = rs < kCB ? lane <= rs : lane <= 2 * (kCB - 1) - rs;
-            if (rs < 2 * kCB - 1 && l <= lmax && in_block && lp >= 0)
-                __builtin_nontemporal_store((2.0 * lp + 1.0) * kInv4Pi * v[u], M + l * n1 + lp);
+            const int sig = sw + 4 * (it0 + u);
+            const int lp = dij + max(sig - (kCI - 1), -sig) + lane;
+            if (ok[u]) __builtin_nontemporal_store((2.0 * lp + 1.0) * kInv4Pi * v[u], M + (i0 + j0 + sig) * n1 + lp);
         }
     }
-    // M[l'][l] (l > l'): row rt = i - j - (i0 - j0) + 63 of the block, one lane per j;
-    // rt < 64: j - j0 = 63 - rt + lane, i - i0 = lane; rt >= 64: j - j0 = lane, i - i0 = rt - 63 + lane
+    // M[l'][l] (l > l'): row tau = l' = i - j, t = tau - (i0 - j0) in [-31, 63]; lane at
+    // c = l - i0 - j0; p = parity of c + t, i - i0 = (c - p + t) / 2, j - j0 = (c - p - t) / 2
 #pragma unroll 1
-    for (int it0 = 0; it0 < kCB / 2; it0 += 8) {
+    for (int it0 = 0; it0 < 24; it0 += 8) {
         double v[8];
+        bool ok[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int rt = sw + 4 * (it0 + u);
-            const int x = rt < kCB ? kSPitch * lane + (kCB - 1) - rt + lane : kSPitch * (rt - (kCB - 1) + lane) + lane;
-            const int xc = x < kCB * kSPitch ? x : 0;
-            v[u] = P0[xc] + P1[xc];
+            const int t = sw + 4 * (it0 + u) - (kCJ - 1);
+            const int c = abs(t) + lane;
+            const int p = (c + t) & 1;
+            const int ii = (c - p + t) >> 1, jj = (c - p - t) >> 1;
+            ok[u] = ii >= 0 && ii < kCI && jj >= 0 && jj < kCJ && dij + t >= 0 && i0 + j0 + c <= lmax &&
+                    (j0 + jj > 0 || p > 0);
+            const int x = ok[u] ? p * kTile + ii * kPitch + jj : 0;
+            v[u] = P0[x] + P1[x];
         }
         asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int rt = sw + 4 * (it0 + u);
-            const int tau = dij - (kCB - 1) + rt;
-            const int jj = rt < kCB ? (kCB - 1) - rt + lane : lane;
-            const int l = 2 * (j0 + jj) + tau + p;   // i + j + p with i = tau + j
-            const bool in_block = rt < kCB ? lane <= rt : lane <= 2 * (kCB - 1) - rt;
-            if (rt < 2 * kCB - 1 && tau >= 0 && in_block && l <= lmax && (j0 + jj > 0 || p > 0))
-                __builtin_nontemporal_store((2.0 * l + 1.0) * kInv4Pi * v[u], M + tau * n1 + l);
+            const int t = sw + 4 * (it0 + u) - (kCJ - 1);
+            const int l = i0 + j0 + abs(t) + lane;
+            if (ok[u]) __builtin_nontemporal_store((2.0 * l + 1.0) * kInv4Pi * v[u], M + (dij + t) * n1 + l);
         }
     }
 }
 
 // Persistent kernel, one workgroup per CU (its LDS keeps a second one off the
 // CU).  Waves 0-3 run the matrix products: each has a SIMD's matrix core to
-// itself and takes a quarter of the k steps of the current block.  Waves 4-7
-// write the previous block to M meanwhile (at a raised issue priority, as the
+// itself and takes a quarter of the k steps of the current unit.  Waves 4-7
+// write the previous unit to M meanwhile (at a raised issue priority, as the
 // matrix waves would otherwise take nearly every issue slot), so that the
 // stores overlap the matrix work instead of following it.  The four partial
-// blocks are summed in LDS as (w0 + w2) + (w1 + w3): waves 2 and 3 hand theirs
+// results are summed in LDS as (w0 + w2) + (w1 + w3): waves 2 and 3 hand theirs
 // to waves 0 and 1 through buffers P0 and P1, which then hold the two sums; two
-// such buffer pairs alternate between consecutive blocks.
+// such buffer pairs alternate between consecutive units.
 __global__ __launch_bounds__(kCouplingThreads, 1) void coupling_mfma_kernel(const double *__restrict__ A,
                                                                            const double *__restrict__ B,
                                                                            const double *__restrict__ T, int lmax,
-                                                                           int kw0, int kw1,
-                                                                           int *__restrict__ counter,
+                                                                           int kw0, int *__restrict__ counter,
                                                                            double *__restrict__ M) {
-    extern __shared__ double Sd[];   // [2 buffer pairs][P0, P1][kCB][kSPitch], kCouplingLds bytes
+    extern __shared__ double Sd[];   // [2 buffer pairs][P0, P1][parity][kCI][kPitch], kCouplingLds bytes
     __shared__ int64_t unit_s;
-    constexpr int kBuf = 2 * kCB * kSPitch;
-    const int L0 = lmax / kCB, L1 = lmax >= 1 ? (lmax - 1) / kCB : -1;
-    const int64_t units = blocks_from(L0, 0) + blocks_from(L1, 0);
+    constexpr int kBuf = 2 * 2 * kTile;
+    const int L0 = lmax / (2 * kCJ), L1 = lmax >= kCJ ? (lmax - kCJ) / (2 * kCJ) : -1;
+    const int64_t units = units_from(L0, 0) + units_from(L1, 0);
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lr = lane & 15, lk = lane >> 4;
-    // thread 0 takes block numbers one block ahead, so that the atomic's latency
-    // is hidden behind the current block
+    // thread 0 takes unit numbers one unit ahead, so that the atomic's latency
+    // is hidden behind the current unit
     int next = 0;
     if (threadIdx.x == 0) {
         unit_s = atomicAdd(counter, 1);
@@ -334,42 +366,46 @@ __global__ __launch_bounds__(kCouplingThreads, 1) void coupling_mfma_kernel(cons
     lds_barrier();
     int64_t u = unit_s;
     if (wave >= 4) __builtin_amdgcn_s_setprio(3);
-    bool pending = false;   // the previous block waits in buffer pair (n - 1) & 1
-    CouplingBlock prev{0, 0, 0};
+    bool pending = false;   // the previous unit waits in buffer pair (n - 1) & 1
+    CouplingUnit prev{0, 0};
     for (int n = 0;; ++n) {
         if (u >= units && !pending) break;
         const bool have = u < units;
-        const CouplingBlock cb = have ? coupling_block(u, L0, L1) : CouplingBlock{0, 0, 0};
+        const CouplingUnit cu = have ? coupling_unit(u, L0, L1) : CouplingUnit{0, 0};
         double *Q = Sd + (n & 1) * kBuf;
         if (wave < 4) {
             if (have) {
-                const int kw = cb.p ? kw1 : kw0;
-                const int ke = min(min(cb.i0 + kCB - 1, lmax - cb.p - cb.j0), kw);
-                v4d acc[4][4];
-                coupling_mma(A, B, T, cb.i0, cb.j0, cb.p, ke, wave, lane, acc);
+                // k range of the parity with the longer one (p = 0): the other's extra terms vanish
+                const int ke = min(min(cu.i0 + kCI - 1, lmax - cu.j0), kw0);
+                v4d acc[2][4][2];
+                coupling_mma(A, B, T, cu.i0, cu.j0, ke, wave, lane, acc);
                 // (16x16 f64 result tile: register r of a lane holds row lane / 16 + 4 r, column lane % 16)
                 if (wave >= 2) {
-                    double *P = Q + (wave - 2) * (kCB * kSPitch);
+                    double *P = Q + (wave - 2) * (2 * kTile);
 #pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
+                    for (int p = 0; p < 2; ++p)
 #pragma unroll
-                        for (int nt = 0; nt < 4; ++nt)
+                        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                P[(16 * mt + lk + 4 * r) * kSPitch + 16 * nt + lr] = acc[mt][nt][r];
+                            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r)
+                                    P[p * kTile + (16 * mt + lk + 4 * r) * kPitch + 16 * nt + lr] = acc[p][mt][nt][r];
                 }
                 lds_barrier();
                 if (wave < 2) {
-                    double *P = Q + wave * (kCB * kSPitch);
+                    double *P = Q + wave * (2 * kTile);
 #pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
+                    for (int p = 0; p < 2; ++p)
 #pragma unroll
-                        for (int nt = 0; nt < 4; ++nt)
+                        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                double *x = P + (16 * mt + lk + 4 * r) * kSPitch + 16 * nt + lr;
-                                *x = acc[mt][nt][r] + *x;
-                            }
+                            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    double *x = P + p * kTile + (16 * mt + lk + 4 * r) * kPitch + 16 * nt + lr;
+                                    *x = acc[p][mt][nt][r] + *x;
+                                }
                 }
             } else {
                 lds_barrier();
@@ -381,13 +417,13 @@ __global__ __launch_bounds__(kCouplingThreads, 1) void coupling_mfma_kernel(cons
         } else {
             if (pending) {
                 const double *P0 = Sd + ((n - 1) & 1) * kBuf;
-                store_block(P0, P0 + kCB * kSPitch, prev.i0, prev.j0, prev.p, wave - 4, lane, lmax, M);
+                store_unit(P0, P0 + 2 * kTile, prev.i0, prev.j0, wave - 4, lane, lmax, M);
             }
             lds_barrier();
         }
-        lds_barrier();   // the block's sums are in Q; unit_s holds the next block
+        lds_barrier();   // the unit's sums are in Q; unit_s holds the next unit
         pending = have;
-        prev = cb;
+        prev = cu;
         u = unit_s;
     }
 }
@@ -672,13 +708,13 @@ hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, dou
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const int lw = lmax_w < 2 * lmax ? lmax_w : 2 * lmax;
-    const int kw0 = lw >> 1, kw1 = lw >= 1 ? (lw - 1) >> 1 : -1;
+    const int kw0 = lw >> 1;   // k range of the even parity (the odd one's extra terms vanish)
     const unsigned grid = (unsigned)(cus > 0 ? cus : 1);
     if ((e = hipFuncSetAttribute((const void *)coupling_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)kCouplingLds)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(coupling_mfma_kernel, dim3(grid), dim3(kCouplingThreads), kCouplingLds, stream,
-                       (const double *)A, (const double *)B, (const double *)T, lmax, kw0, kw1, counter, M);
+                       (const double *)A, (const double *)B, (const double *)T, lmax, kw0, counter, M);
     return hipGetLastError();
 }
 
