@@ -25,6 +25,9 @@
 // partial pivoting in one workgroup, then forward and back substitution for all
 // right-hand sides at once, a panel of columns per workgroup.  Normalised:
 // C~' = N theta C^, cal M' = N theta M, 1/N = sum_l (2l+1) W_l / (4 pi).
+#include <map>
+#include <mutex>
+
 #include "ptalm_internal.h"
 
 namespace ptalm {
@@ -704,15 +707,27 @@ hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, dou
                        counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // the CU count and the kernel's LDS attribute, once per device (host calls
+    // between the two launches would leave the GPU idle after the tables kernel)
+    static std::mutex mu;
+    static std::map<int, int> cus_of;
     int dev = 0, cus = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cus_of.find(dev);
+        if (it == cus_of.end()) {
+            if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+            if ((e = hipFuncSetAttribute((const void *)coupling_mfma_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCouplingLds)) != hipSuccess)
+                return e;
+            it = cus_of.emplace(dev, cus > 0 ? cus : 1).first;
+        }
+        cus = it->second;
+    }
     const int lw = lmax_w < 2 * lmax ? lmax_w : 2 * lmax;
     const int kw0 = lw >> 1;   // k range of the even parity (the odd one's extra terms vanish)
-    const unsigned grid = (unsigned)(cus > 0 ? cus : 1);
-    if ((e = hipFuncSetAttribute((const void *)coupling_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)kCouplingLds)) != hipSuccess)
-        return e;
+    const unsigned grid = (unsigned)cus;
     hipLaunchKernelGGL(coupling_mfma_kernel, dim3(grid), dim3(kCouplingThreads), kCouplingLds, stream,
                        (const double *)A, (const double *)B, (const double *)T, lmax, kw0, counter, M);
     return hipGetLastError();
