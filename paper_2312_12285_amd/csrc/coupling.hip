@@ -284,18 +284,19 @@ __device__ inline void coupling_mma(const double *__restrict__ A, const double *
 // the store conditions).  M is written once and not read here: streaming stores
 // keep the tables in the caches.
 __device__ inline void store_unit(const double *__restrict__ P0, const double *__restrict__ P1, int i0, int j0,
-                                  int sw, int lane, int lmax, double *__restrict__ M) {
+                                  int sw, int nw, int lane, int lmax, double *__restrict__ M) {
+    const int rows = (3 * kCJ + nw - 1) / nw;   // rows per wave in each triangle (the last ones may fall outside)
     const int64_t n1 = lmax + 1;
     const int dij = i0 - j0;
     // M[l][l'] (l >= l'): row sig = l - i0 - j0 in [0, 95]; lane at c = l' - (i0 - j0);
     // p = parity of sig + c, i - i0 = (sig - p + c) / 2, j - j0 = (sig - p - c) / 2
 #pragma unroll 1
-    for (int it0 = 0; it0 < 24; it0 += 8) {
+    for (int it0 = 0; it0 < rows; it0 += 8) {
         double v[8];
         bool ok[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int sig = sw + 4 * (it0 + u);
+            const int sig = sw + nw * (it0 + u);
             const int c = max(sig - (kCI - 1), -sig) + lane;
             const int p = (sig + c) & 1;
             const int ii = (sig - p + c) >> 1, jj = (sig - p - c) >> 1;
@@ -306,7 +307,7 @@ __device__ inline void store_unit(const double *__restrict__ P0, const double *_
         asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int sig = sw + 4 * (it0 + u);
+            const int sig = sw + nw * (it0 + u);
             const int lp = dij + max(sig - (kCI - 1), -sig) + lane;
             if (ok[u]) __builtin_nontemporal_store((2.0 * lp + 1.0) * kInv4Pi * v[u], M + (i0 + j0 + sig) * n1 + lp);
         }
@@ -314,12 +315,12 @@ __device__ inline void store_unit(const double *__restrict__ P0, const double *_
     // M[l'][l] (l > l'): row tau = l' = i - j, t = tau - (i0 - j0) in [-31, 63]; lane at
     // c = l - i0 - j0; p = parity of c + t, i - i0 = (c - p + t) / 2, j - j0 = (c - p - t) / 2
 #pragma unroll 1
-    for (int it0 = 0; it0 < 24; it0 += 8) {
+    for (int it0 = 0; it0 < rows; it0 += 8) {
         double v[8];
         bool ok[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int t = sw + 4 * (it0 + u) - (kCJ - 1);
+            const int t = sw + nw * (it0 + u) - (kCJ - 1);
             const int c = abs(t) + lane;
             const int p = (c + t) & 1;
             const int ii = (c - p + t) >> 1, jj = (c - p - t) >> 1;
@@ -331,7 +332,7 @@ __device__ inline void store_unit(const double *__restrict__ P0, const double *_
         asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int t = sw + 4 * (it0 + u) - (kCJ - 1);
+            const int t = sw + nw * (it0 + u) - (kCJ - 1);
             const int l = i0 + j0 + abs(t) + lane;
             if (ok[u]) __builtin_nontemporal_store((2.0 * l + 1.0) * kInv4Pi * v[u], M + (dij + t) * n1 + l);
         }
@@ -376,53 +377,49 @@ __global__ __launch_bounds__(kCouplingThreads, 1) void coupling_mfma_kernel(cons
         const bool have = u < units;
         const CouplingUnit cu = have ? coupling_unit(u, L0, L1) : CouplingUnit{0, 0};
         double *Q = Sd + (n & 1) * kBuf;
-        if (wave < 4) {
-            if (have) {
-                // k range of the parity with the longer one (p = 0): the other's extra terms vanish
-                const int ke = min(min(cu.i0 + kCI - 1, lmax - cu.j0), kw0);
-                v4d acc[2][4][2];
-                coupling_mma(A, B, T, cu.i0, cu.j0, ke, wave, lane, acc);
-                // (16x16 f64 result tile: register r of a lane holds row lane / 16 + 4 r, column lane % 16)
-                if (wave >= 2) {
-                    double *P = Q + (wave - 2) * (2 * kTile);
+        if (wave < 4 && have) {
+            const int ke = min(min(cu.i0 + kCI - 1, lmax - cu.j0), kw0);
+            v4d acc[2][4][2];
+            coupling_mma(A, B, T, cu.i0, cu.j0, ke, wave, lane, acc);
+            // (16x16 f64 result tile: register r of a lane holds row lane / 16 + 4 r, column lane % 16)
+            if (wave >= 2) {
+                double *P = Q + (wave - 2) * (2 * kTile);
 #pragma unroll
-                    for (int p = 0; p < 2; ++p)
+                for (int p = 0; p < 2; ++p)
 #pragma unroll
-                        for (int mt = 0; mt < 4; ++mt)
+                    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                            for (int nt = 0; nt < 2; ++nt)
+                        for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-                                for (int r = 0; r < 4; ++r)
-                                    P[p * kTile + (16 * mt + lk + 4 * r) * kPitch + 16 * nt + lr] = acc[p][mt][nt][r];
-                }
-                lds_barrier();
-                if (wave < 2) {
-                    double *P = Q + wave * (2 * kTile);
-#pragma unroll
-                    for (int p = 0; p < 2; ++p)
-#pragma unroll
-                        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                            for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) {
-                                    double *x = P + p * kTile + (16 * mt + lk + 4 * r) * kPitch + 16 * nt + lr;
-                                    *x = acc[p][mt][nt][r] + *x;
-                                }
-                }
-            } else {
-                lds_barrier();
-            }
-            if (threadIdx.x == 0) {
-                unit_s = next;
-                next = atomicAdd(counter, 1);
-            }
-        } else {
-            if (pending) {
-                const double *P0 = Sd + ((n - 1) & 1) * kBuf;
-                store_unit(P0, P0 + 2 * kTile, prev.i0, prev.j0, wave - 4, lane, lmax, M);
+                            for (int r = 0; r < 4; ++r)
+                                P[p * kTile + (16 * mt + lk + 4 * r) * kPitch + 16 * nt + lr] = acc[p][mt][nt][r];
             }
             lds_barrier();
+            if (wave < 2) {
+                double *P = Q + wave * (2 * kTile);
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                double *x = P + p * kTile + (16 * mt + lk + 4 * r) * kPitch + 16 * nt + lr;
+                                *x = acc[p][mt][nt][r] + *x;
+                            }
+            }
+        } else {
+            // the store waves write the previous unit; after the last unit all eight waves do
+            if (pending && (wave >= 4 || !have)) {
+                const double *P0 = Sd + ((n - 1) & 1) * kBuf;
+                store_unit(P0, P0 + 2 * kTile, prev.i0, prev.j0, have ? wave - 4 : wave, have ? 4 : 8, lane, lmax, M);
+            }
+            lds_barrier();
+        }
+        if (threadIdx.x == 0) {
+            unit_s = next;
+            next = atomicAdd(counter, 1);
         }
         lds_barrier();   // the unit's sums are in Q; unit_s holds the next unit
         pending = have;
