@@ -675,7 +675,7 @@ def run_coupling(args):
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": recorded_traffic(args.workload, "tables+mfma per call"),
-                "kernel": "coupling_tables_kernel + coupling_mfma_kernel (one ptalm_coupling_matrix call)",
+                "kernel": "coupling_t_kernel + coupling_mfma_kernel (one ptalm_coupling_matrix call)",
                 "kernel_ms_per_launch": round(k_ms, 4), "flops_per_term": 2,
                 "terms_per_launch": half_terms}
     line = {"metric": "coupling-sum terms (l,l',lambda)/s, mode coupling + bandpowers", "value": terms * steps / elapsed,

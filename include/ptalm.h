@@ -173,7 +173,12 @@ int ptalm_window_shot_noise(const double *w, int64_t n, const double *alpha, dou
  * FP64.  With J = (l + l' + lambda)/2 and a(n) = binom(2n, n)/4^n the 3j square
  * is a(J-l) a(J-l') a(J-lambda) / ((2J+1) a(J)); the matrix is computed as a
  * triangular matrix product on the matrix cores from tables of a(n) (the same
- * values the App. B recurrence gives).  Allocates stream-ordered scratch.
+ * values the App. B recurrence gives).  Allocates stream-ordered scratch.  The
+ * tables that depend on lmax only (a(n) and 1/((2J+1) a(J)), about 3 lmax
+ * doubles) are kept per (device, lmax) for the rest of the process: the first
+ * call for an lmax outside stream capture allocates them and waits for them once
+ * (a synchronisation of `stream`); under capture an lmax not seen before
+ * computes them into the call's scratch instead, so the call stays capturable.
  * PTALM_EINVAL on bad sizes or NULL pointers. */
 int ptalm_coupling_matrix(const double *Wl, int lmax_w, const double *shot, int lmax, double *M, void *stream);
 

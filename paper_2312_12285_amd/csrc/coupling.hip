@@ -84,30 +84,22 @@ constexpr int kTabPad = 128;   // zeros on either side of each coupling table
 //   A[n] = a(n) = prod_{m=1..n} (2m-1)/(2m)       n in [0, lmax]
 //   B[J] = 1 / ((2J+1) a(J))                      J in [0, 2 lmax]
 //   T[lambda] = (2 lambda + 1)(W_lambda - shot)   lambda in [0, 2 lmax + 1], 0 beyond lmax_w
-// (A, B and T point at entry 0).  a(n) is a prefix product, taken in
-// double-double: each thread multiplies its chunk of factors; a scan within each
-// wave (lane shuffles) and one over the 16 wave totals (through LDS, one barrier)
-// give each chunk its starting value.
-__global__ __launch_bounds__(kTabThreads) void coupling_tables_kernel(const double *__restrict__ Wl, int lmax_w,
-                                                                      const double *__restrict__ shot, int lmax,
-                                                                      double *__restrict__ A, double *__restrict__ B,
-                                                                      double *__restrict__ T,
-                                                                      int *__restrict__ counter) {
+// (A, B and T point at entry 0).  A and B depend on lmax only.  a(n) is a prefix
+// product, taken in double-double: each thread multiplies its chunk of factors;
+// a scan within each wave (lane shuffles) and one over the 16 wave totals
+// (through LDS, one barrier) give each chunk its starting value.
+__global__ __launch_bounds__(kTabThreads) void coupling_ab_kernel(int lmax, double *__restrict__ A,
+                                                                  double *__restrict__ B) {
     constexpr int kWaves = kTabThreads / 64;
     __shared__ double wh[kWaves], wl[kWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) *counter = 0;   // unit counter of coupling_mfma_kernel
     const int N = 2 * lmax + 1;
     for (int e = tid; e < kTabPad; e += kTabThreads) {
         A[e - kTabPad] = 0.0;
         A[lmax + 1 + e] = 0.0;
         B[e - kTabPad] = 0.0;
         B[N + e] = 0.0;
-        T[e - kTabPad] = 0.0;
-        T[N + 1 + e] = 0.0;
     }
-    const double sub = shot ? shot[0] : 0.0;
-    for (int lam = tid; lam <= N; lam += kTabThreads) T[lam] = lam <= lmax_w ? (2.0 * lam + 1.0) * (Wl[lam] - sub) : 0.0;
     const int chunk = (N + kTabThreads - 1) / kTabThreads;
     const int n_lo = tid * chunk < N ? tid * chunk : N;
     const int n_hi = n_lo + chunk < N ? n_lo + chunk : N;
@@ -132,6 +124,17 @@ __global__ __launch_bounds__(kTabThreads) void coupling_tables_kernel(const doub
         const double q = recip(dh);
         B[n] = fma(q, fma(-q, dh, 1.0) - q * dl, q);
     }
+}
+
+// T with its padding, and the unit counter of coupling_mfma_kernel set to 0
+__global__ __launch_bounds__(kTabThreads) void coupling_t_kernel(const double *__restrict__ Wl, int lmax_w,
+                                                                 const double *__restrict__ shot, int lmax,
+                                                                 double *__restrict__ T, int *__restrict__ counter) {
+    const int N = 2 * lmax + 1;
+    const double sub = shot ? shot[0] : 0.0;
+    const int e = blockIdx.x * kTabThreads + threadIdx.x - kTabPad;   // lambda, from -kTabPad
+    if (e == -kTabPad) *counter = 0;
+    if (e < N + 1 + kTabPad) T[e] = e >= 0 && e <= lmax_w && e <= N ? (2.0 * e + 1.0) * (Wl[e] - sub) : 0.0;
 }
 
 // Workgroup barrier that orders LDS accesses only: global stores still in
@@ -694,22 +697,67 @@ size_t coupling_scratch_doubles(int lmax) {
     return (L + 1) + (2 * L + 1) + (2 * L + 2) + 6 * kTabPad + 1;
 }
 
+namespace {
+
+// A and B of coupling_ab_kernel for (device, lmax), kept for the process: built by
+// the first call for that lmax outside stream capture (which waits for them once)
+struct AbTables {
+    double *buf;   // [pad | A | pad | pad | B | pad]
+    const double *A() const { return buf + kTabPad; }
+};
+std::mutex g_ab_mu;
+std::map<std::pair<int, int>, AbTables> g_ab;
+
+}  // namespace
+
 hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, double *scratch, int lmax, double *M,
                            hipStream_t stream) {
+    // scratch: [pad | A | pad | pad | B | pad | pad | T | pad | counter]; A and B are
+    // used only when the cached tables are not there (first call under capture)
     double *A = scratch + kTabPad;
     double *B = A + (lmax + 1) + 2 * kTabPad;
     double *T = B + (2 * lmax + 1) + 2 * kTabPad;
     int *counter = (int *)(T + (2 * lmax + 2) + kTabPad);
-    hipLaunchKernelGGL(coupling_tables_kernel, dim3(1), dim3(kTabThreads), 0, stream, Wl, lmax_w, shot, lmax, A, B, T,
-                       counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const size_t ab_doubles = (size_t)(lmax + 1) + (2 * lmax + 1) + 4 * kTabPad;
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    const double *Ause = A, *Buse = B;
+    {
+        std::lock_guard<std::mutex> lock(g_ab_mu);
+        auto it = g_ab.find({dev, lmax});
+        if (it == g_ab.end()) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if ((e = hipStreamIsCapturing(stream, &cs)) != hipSuccess) return e;
+            if (cs == hipStreamCaptureStatusNone) {
+                double *buf = nullptr;
+                if ((e = hipMalloc((void **)&buf, sizeof(double) * ab_doubles)) != hipSuccess) return e;
+                double *a = buf + kTabPad, *b = a + (lmax + 1) + 2 * kTabPad;
+                hipLaunchKernelGGL(coupling_ab_kernel, dim3(1), dim3(kTabThreads), 0, stream, lmax, a, b);
+                if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(stream)) != hipSuccess) {
+                    (void)hipFree(buf);
+                    return e;
+                }
+                it = g_ab.emplace(std::make_pair(dev, lmax), AbTables{buf}).first;
+            }
+        }
+        if (it != g_ab.end()) {
+            Ause = it->second.A();
+            Buse = Ause + (lmax + 1) + 2 * kTabPad;
+        } else {
+            hipLaunchKernelGGL(coupling_ab_kernel, dim3(1), dim3(kTabThreads), 0, stream, lmax, A, B);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    const int nt = 2 * lmax + 2 + 2 * kTabPad;
+    hipLaunchKernelGGL(coupling_t_kernel, dim3((nt + kTabThreads - 1) / kTabThreads), dim3(kTabThreads), 0, stream, Wl,
+                       lmax_w, shot, lmax, T, counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     // the CU count and the kernel's LDS attribute, once per device (host calls
-    // between the two launches would leave the GPU idle after the tables kernel)
+    // between the launches would leave the GPU idle)
     static std::mutex mu;
     static std::map<int, int> cus_of;
-    int dev = 0, cus = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    int cus = 0;
     {
         std::lock_guard<std::mutex> lock(mu);
         auto it = cus_of.find(dev);
@@ -725,8 +773,8 @@ hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, dou
     const int lw = lmax_w < 2 * lmax ? lmax_w : 2 * lmax;
     const int kw0 = lw >> 1;   // k range of the even parity (the odd one's extra terms vanish)
     const unsigned grid = (unsigned)cus;
-    hipLaunchKernelGGL(coupling_mfma_kernel, dim3(grid), dim3(kCouplingThreads), kCouplingLds, stream,
-                       (const double *)A, (const double *)B, (const double *)T, lmax, kw0, counter, M);
+    hipLaunchKernelGGL(coupling_mfma_kernel, dim3(grid), dim3(kCouplingThreads), kCouplingLds, stream, Ause, Buse,
+                       (const double *)T, lmax, kw0, counter, M);
     return hipGetLastError();
 }
 

@@ -50,6 +50,42 @@ def test_coupling_matrix_matches_oracle(lib, oracle, lmax, lmax_w):
     assert rel.size == 0 or rel.max() <= 1e-12
 
 
+def test_coupling_capture_and_table_cache(lib, oracle):
+    """The lmax-only tables are kept per (device, lmax) after the first call outside
+    capture; a call captured for an lmax not seen before computes them into its own
+    scratch.  Graph replays of both forms equal the eager call bit for bit, with
+    eager work between the replays, and match the oracle."""
+    import torch
+    lmax, lmax_w = 333, 700      # an lmax no other test uses, so the first call below is captured
+    rng = np.random.default_rng(333)
+    W = np.abs(rng.normal(size=lmax_w + 1)) * np.exp(-np.arange(lmax_w + 1) / 30.0)
+    W[0] = 4 * math.pi * 0.3
+    Wd = dev(W)
+    out = torch.empty((lmax + 1, lmax + 1), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    graphs = []
+    for form in ("tables in the call's scratch", "kept tables"):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            lib.coupling_matrix(Wd, lmax, out=out)
+        graphs.append((form, g))
+        if form.startswith("tables"):
+            eager = lib.coupling_matrix(Wd, lmax)     # first call outside capture: keeps the tables
+            torch.cuda.synchronize()
+    for form, g in graphs:
+        for rep in range(3):
+            out.fill_(-1.0)                           # eager work between replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), f"{form}: replay {rep} differs from the eager call"
+    ref = oracle.coupling_matrix(W, lmax)
+    M = host(eager)
+    nz = ref != 0
+    assert np.array_equal(M == 0, ~nz)
+    assert (np.abs(M[nz] - ref[nz]) / ref[nz]).max() <= 1e-12
+
+
 def test_full_sky_identity(lib):
     W = np.zeros(600)
     W[0] = 4 * math.pi
