@@ -533,6 +533,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(double *__restrict__ Ag,
 }
 
 constexpr int kSolveThreads = 256;
+constexpr int kLuPB = 16;   // row block of the triangular solves
 constexpr int kSolveLds = 20224;   // doubles of LDS per workgroup (factors and/or right-hand sides)
 
 // Columns of the right-hand sides per workgroup of lu_solve_kernel, and whether
@@ -585,16 +586,59 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(const double *_
         X[i * cols + c] = v;
     }
     __syncthreads();
-    for (int k = 0; k < nb - 1; ++k) {   // L y = P b
-        const double xk = X[k * cols + c];
-        for (int i = k + 1 + r0; i < nb; i += rstep) X[i * cols + c] = fma(-LU[i * nb + k], xk, X[i * cols + c]);
+    // L y = P b and then U x = y, by row blocks of kLuPB: a block's own rows are
+    // solved in registers, one thread per column, then the rows beyond it are
+    // updated by every thread.  Each entry receives the same multiply-adds in the
+    // same order as in the row-by-row substitution (forward: ascending j; back:
+    // descending j), so the result is the same bit for bit.
+    for (int rb = 0; rb < nb; rb += kLuPB) {
+        const int re = min(rb + kLuPB, nb);
+        if (r0 == 0) {
+            double xb[kLuPB];
+#pragma unroll
+            for (int a = 0; a < kLuPB; ++a) xb[a] = rb + a < re ? X[(rb + a) * cols + c] : 0.0;
+#pragma unroll
+            for (int a = 1; a < kLuPB; ++a)
+                if (rb + a < re) {
+#pragma unroll
+                    for (int j = 0; j < a; ++j) xb[a] = fma(-LU[(rb + a) * nb + rb + j], xb[j], xb[a]);
+                }
+#pragma unroll
+            for (int a = 1; a < kLuPB; ++a)
+                if (rb + a < re) X[(rb + a) * cols + c] = xb[a];
+        }
+        __syncthreads();
+        for (int i = re + r0; i < nb; i += rstep) {
+            double t = X[i * cols + c];
+            for (int j = rb; j < re; ++j) t = fma(-LU[i * nb + j], X[j * cols + c], t);
+            X[i * cols + c] = t;
+        }
         __syncthreads();
     }
-    for (int k = nb - 1; k >= 0; --k) {   // U x = y
-        const double xk = X[k * cols + c] / LU[k * nb + k];
+    for (int re = nb; re > 0; re -= kLuPB) {
+        const int rb = max(re - kLuPB, 0);
+        if (r0 == 0) {
+            double xb[kLuPB];   // xb[a] holds row re - 1 - a
+#pragma unroll
+            for (int a = 0; a < kLuPB; ++a) xb[a] = re - 1 - a >= rb ? X[(re - 1 - a) * cols + c] : 0.0;
+#pragma unroll
+            for (int a = 0; a < kLuPB; ++a)
+                if (re - 1 - a >= rb) {
+                    const int i = re - 1 - a;
+#pragma unroll
+                    for (int j = 0; j < a; ++j) xb[a] = fma(-LU[i * nb + (re - 1 - j)], xb[j], xb[a]);
+                    xb[a] = xb[a] / LU[i * nb + i];
+                }
+#pragma unroll
+            for (int a = 0; a < kLuPB; ++a)
+                if (re - 1 - a >= rb) X[(re - 1 - a) * cols + c] = xb[a];
+        }
         __syncthreads();
-        if (r0 == 0) X[k * cols + c] = xk;
-        for (int i = r0; i < k; i += rstep) X[i * cols + c] = fma(-LU[i * nb + k], xk, X[i * cols + c]);
+        for (int i = r0; i < rb; i += rstep) {
+            double t = X[i * cols + c];
+            for (int j = re - 1; j >= rb; --j) t = fma(-LU[i * nb + j], X[j * cols + c], t);
+            X[i * cols + c] = t;
+        }
         __syncthreads();
     }
     if (!live) return;
