@@ -62,10 +62,11 @@ __global__ void nodes_kernel(double theta_cut, double h, int n_nodes, double *__
 //   bucket_start_kernel H[c][b] <- offsets[b] + sum_{c' < c} H[c'][b], the place
 //                       of the first point of chunk c in bucket b;
 //   stable_scatter_kernel each wavefront walks its chunk in input order, 64
-//                       points per round; lanes whose points share a bucket are
-//                       ranked by lane index (one ballot per distinct bucket), so
-//                       a point's place is its chunk's start in its bucket plus
-//                       the points of that bucket before it in the chunk.
+//                       points per round; each lane compares its bucket with
+//                       every other lane's (lane shuffles), which gives its rank
+//                       among the lower lanes of the same bucket, so a point's
+//                       place is its chunk's start in its bucket plus the points
+//                       of that bucket before it in the chunk.
 // Buckets are handled in windows of kHistMax (one LDS array per wavefront), one
 // pass over the chunk per window.
 constexpr int kHistMax = 16384;      // buckets per LDS window (64 KB)
@@ -81,7 +82,8 @@ __device__ inline void wave_sync_lds() {
 __global__ __launch_bounds__(64) void chunk_hist_kernel(const double *__restrict__ theta, int64_t n, double theta_cut,
                                                         double h, int n_int, int64_t chunk,
                                                         unsigned *__restrict__ H) {
-    __shared__ unsigned hist[kHistMax];
+    extern __shared__ unsigned hist[];   // min(nb, kHistMax) counters (dynamic, so that small bucket counts
+                                         // leave room for more wavefronts per CU)
     const int nb = n_int + 1;
     const int64_t c = blockIdx.x;
     const int64_t lo = c * chunk;
@@ -131,13 +133,12 @@ __global__ __launch_bounds__(64) void stable_scatter_kernel(
     double theta_cut, double h, int n_int, int64_t chunk, const double *__restrict__ xn,
     const int64_t *__restrict__ offsets, const unsigned *__restrict__ start, double *__restrict__ q,
     double *__restrict__ pth, double *__restrict__ pph, double *__restrict__ pw) {
-    __shared__ unsigned cur[kHistMax];
+    extern __shared__ unsigned cur[];   // min(nb, kHistMax) cursors (dynamic, as in chunk_hist_kernel)
     const int nb = n_int + 1;
     const int lane = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int64_t lo = c * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes with a lower index
     for (int w0 = 0; w0 < nb; w0 += kHistMax) {
         const int wn = nb - w0 < kHistMax ? nb - w0 : kHistMax;
         for (int b = lane; b < wn; b += 64) cur[b] = start[c * nb + w0 + b];
@@ -151,18 +152,22 @@ __global__ __launch_bounds__(64) void stable_scatter_kernel(
                 j = interval_of(th, theta_cut, h, n_int);
             }
             const bool act = j >= w0 && j < w0 + wn;
-            uint64_t todo = __ballot(act);
-            unsigned pos = 0u;
-            while (todo) {
-                const int leader = __builtin_ctzll(todo);
-                const int jj = __builtin_amdgcn_readlane(j, leader);
-                const bool mine = act && j == jj;
-                const uint64_t same = __ballot(mine);
-                const unsigned b0 = cur[jj - w0];
-                if (mine) pos = b0 + (unsigned)__popcll(same & below);
-                if (lane == leader) cur[jj - w0] = b0 + (unsigned)__popcll(same);
-                todo &= ~same;
+            // rank among the lower lanes of the same bucket, and whether no higher
+            // lane shares it: compared against every other lane's bucket (lane
+            // lane - r after r steps), so the round needs no serial pass per bucket
+            const int jm = act ? j : -1 - lane;   // inactive lanes match no one
+            int lower = 0;
+            bool last = true;
+#pragma unroll 8
+            for (int r = 1; r < 64; ++r) {
+                const bool eq = __shfl(jm, (lane - r) & 63) == jm;
+                lower += (eq && r <= lane) ? 1 : 0;
+                last = last && !(eq && r > lane);
             }
+            unsigned pos = 0u;
+            if (act) pos = cur[j - w0] + (unsigned)lower;
+            if (act && last) cur[j - w0] = pos + 1u;
+            wave_sync_lds();
             if (!act) continue;
             const double ph = phi[i], wi = w[i];
             if (j == n_int) {
@@ -711,7 +716,8 @@ hipError_t launch_spline_sort(const double *theta, const double *phi, const doub
     hipLaunchKernelGGL(nodes_kernel, dim3((n_nodes + 255) / 256), dim3(256), 0, stream, theta_cut, h, n_nodes, xn, thn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(chunk_hist_kernel, dim3(p.sort_chunks), dim3(64), 0, stream, theta, n, theta_cut, h, nb - 1,
+    const size_t win_bytes = sizeof(unsigned) * (size_t)(nb < kHistMax ? nb : kHistMax);
+    hipLaunchKernelGGL(chunk_hist_kernel, dim3(p.sort_chunks), dim3(64), win_bytes, stream, theta, n, theta_cut, h, nb - 1,
                        p.sort_chunk, H);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(bucket_total_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, (const unsigned *)H,
@@ -722,7 +728,7 @@ hipError_t launch_spline_sort(const double *theta, const double *phi, const doub
     hipLaunchKernelGGL(bucket_start_kernel, dim3((nb + 255) / 256), dim3(256), 0, stream, H, p.sort_chunks, nb,
                        (const int64_t *)offsets, n_polar);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(stable_scatter_kernel, dim3(p.sort_chunks), dim3(64), 0, stream, theta, phi, w, n, theta_cut, h,
+    hipLaunchKernelGGL(stable_scatter_kernel, dim3(p.sort_chunks), dim3(64), win_bytes, stream, theta, phi, w, n, theta_cut, h,
                        nb - 1, p.sort_chunk, (const double *)xn, (const int64_t *)offsets, (const unsigned *)H, q, pth,
                        pph, pw);
     return hipGetLastError();
