@@ -409,8 +409,9 @@ const char *ptalm_server_last_error(void);
 /* Message of the last failed call on this thread ("" if none). Host only. */
 const char *ptalm_last_error(void);
 
-/* Frees the per-device tables cached by earlier calls (coefficients per lmax)
- * and forgets the autotuner's choices.
+/* Frees the per-device tables cached by earlier calls (coefficients per lmax,
+ * the lmax-only tables of the mode coupling) and forgets the autotuner's
+ * choices.  PTALM_EDEVICE with the first failed free's message, else PTALM_OK.
  * Call only when no work of this library is pending on the current device. */
 int ptalm_release_cache(void);
 

@@ -75,11 +75,12 @@ int get_tables(int lmax, const ptalm::Tables **out, bool may_build = true) {
     if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
     e = ptalm::build_tables(lmax, &t, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipStreamDestroy(s);
+    const hipError_t ed = hipStreamDestroy(s);
+    if (e == hipSuccess) e = ed;
     if (e != hipSuccess) {
-        hipFree(t.coef);
-        hipFree(t.coef32);
-        hipFree(t.sigma);
+        (void)hipFree(t.coef);
+        (void)hipFree(t.coef32);
+        (void)hipFree(t.sigma);
         return fail_hip(e, "building coefficient tables");
     }
     auto res = g_tables.emplace(std::make_pair(dev, lmax), t);
@@ -132,7 +133,7 @@ int get_ranges(int lmax, int R, const int **out, bool may_build = true) {
     if (e != hipSuccess) return fail_hip(e, "hipMalloc(ranges)");
     e = hipMemcpy(d, b.data(), sizeof(int) * (R + 1), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        hipFree(d);
+        (void)hipFree(d);
         return fail_hip(e, "hipMemcpy(ranges)");
     }
     g_ranges[key] = d;
@@ -525,7 +526,7 @@ struct AsyncAllocs {
         ptrs.clear();
         return first;
     }
-    ~AsyncAllocs() { release(); }
+    ~AsyncAllocs() { (void)release(); }   // errors of a late release have no caller to go to
 };
 
 }  // namespace
@@ -716,10 +717,11 @@ int get_spin_tables(int lmax, const ptalm::SpinTables **out) {
     if (e != hipSuccess) return fail_hip(e, "hipStreamCreate");
     e = ptalm::build_spin_tables(lmax, &t, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipStreamDestroy(s);
+    const hipError_t ed = hipStreamDestroy(s);
+    if (e == hipSuccess) e = ed;
     if (e != hipSuccess) {
-        hipFree(t.coef);
-        hipFree(t.sigma);
+        (void)hipFree(t.coef);
+        (void)hipFree(t.sigma);
         return fail_hip(e, "building spin tables");
     }
     auto res = g_spin_tables.emplace(std::make_pair(dev, lmax), t);
@@ -1003,8 +1005,8 @@ int ptalm_autotune(const double *theta, const double *phi, const double *w, int6
             pick = cands[c];
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     e = hipFreeAsync(buf, stream);
     if (rc == PTALM_OK && e != hipSuccess) rc = fail_hip(e, "hipFreeAsync");
     if (rc) return rc;
@@ -1024,22 +1026,30 @@ int ptalm_autotune(const double *theta, const double *phi, const double *w, int6
 }
 
 int ptalm_release_cache(void) {
+    g_error.clear();
     std::lock_guard<std::mutex> lock(g_mu);
+    hipError_t first = hipSuccess;
+    auto release = [&](void *p) {
+        const hipError_t e = hipFree(p);
+        if (first == hipSuccess) first = e;
+    };
     for (auto &kv : g_tables) {
-        hipFree(kv.second.coef);
-        hipFree(kv.second.coef32);
-        hipFree(kv.second.sigma);
+        release(kv.second.coef);
+        release(kv.second.coef32);
+        release(kv.second.sigma);
     }
     g_tables.clear();
     for (auto &kv : g_spin_tables) {
-        hipFree(kv.second.coef);
-        hipFree(kv.second.sigma);
+        release(kv.second.coef);
+        release(kv.second.sigma);
     }
     g_spin_tables.clear();
-    for (auto &kv : g_ranges) hipFree(kv.second);
+    for (auto &kv : g_ranges) release(kv.second);
     g_ranges.clear();
     g_tuned.clear();
-    return PTALM_OK;
+    const hipError_t ec = ptalm::release_coupling_tables();
+    if (first == hipSuccess) first = ec;
+    return first == hipSuccess ? PTALM_OK : fail_hip(first, "hipFree (release_cache)");
 }
 
 }  // extern "C"

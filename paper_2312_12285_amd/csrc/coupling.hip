@@ -754,6 +754,17 @@ std::map<std::pair<int, int>, AbTables> g_ab;
 
 }  // namespace
 
+hipError_t release_coupling_tables() {
+    std::lock_guard<std::mutex> lock(g_ab_mu);
+    hipError_t first = hipSuccess;
+    for (auto &kv : g_ab) {
+        const hipError_t e = hipFree(kv.second.buf);
+        if (first == hipSuccess) first = e;
+    }
+    g_ab.clear();
+    return first;
+}
+
 hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, double *scratch, int lmax, double *M,
                            hipStream_t stream) {
     // scratch: [pad | A | pad | pad | B | pad | pad | T | pad | counter]; A and B are

@@ -148,6 +148,8 @@ bool fp32_variant_exists(int kp, int lb, int mode);
 int bandpower_count(int lmax, int lmin, int delta_l);
 size_t bandpower_scratch_doubles(int lmax, int nb);
 size_t coupling_scratch_doubles(int lmax);
+// frees the lmax-only coupling tables kept per (device, lmax); the first hipFree error, else hipSuccess
+hipError_t release_coupling_tables();
 hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, double *scratch, int lmax, double *M,
                            hipStream_t stream);
 hipError_t launch_bandpowers(const double *cl_hat, const double *M, const double *Wl, int lmax_w, int lmax, int lmin,

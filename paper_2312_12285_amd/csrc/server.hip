@@ -240,8 +240,9 @@ int ptalm_server_create(int device, size_t arena_bytes, int slots, ptalm_server 
     }
     (void)hipSetDevice(prev);
     if (rc != PTALM_OK) {
-        for (hipStream_t st : s->streams) hipStreamDestroy(st);
-        if (s->arena) hipFree(s->arena);
+        // clean-up after a failed creation: the first error is the one reported
+        for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        if (s->arena) (void)hipFree(s->arena);
         delete s;
         return rc;
     }
@@ -349,9 +350,10 @@ int ptalm_server_destroy(ptalm_server *s) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
-    for (hipEvent_t ev : s->spare_events) hipEventDestroy(ev);
-    for (hipStream_t st : s->streams) hipStreamDestroy(st);
-    hipFree(s->arena);
+    // teardown: nothing pending remains, and errors here have no caller to report to
+    for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    (void)hipFree(s->arena);
     (void)hipSetDevice(prev);
     delete s;
     return PTALM_OK;
