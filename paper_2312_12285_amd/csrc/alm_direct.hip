@@ -295,14 +295,6 @@ __global__ __launch_bounds__(64) void alm_direct_kernel(AlmArgs args) {
     }
 }
 
-// Neumaier's compensated addition: sum + c carries the exact running total to
-// within one rounding of the final result, whatever the order of magnitudes.
-__device__ inline void neumaier_add(double &sum, double &c, double v) {
-    const double t = sum + v;
-    c += (fabs(sum) >= fabs(v)) ? (sum - t) + v : (v - t) + sum;
-    sum = t;
-}
-
 // Second pass: a_lm = sigma_lm * sum_{s<S} partial_s[l, m], slices in order, in
 // FP64 with compensation (the cross-slice sum is the last reduction of every form,
 // so the reduced-precision forms end in a compensated FP64 reduction too).

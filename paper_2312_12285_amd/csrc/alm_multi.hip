@@ -52,7 +52,8 @@ constexpr int kHalf = kG / 2;    // points of one half: the K range of one wavef
 constexpr int kLT = 32;          // l values per tile
 constexpr int kRowA = kG + 8;    // padded LDS row of an A tile (bf16): rows land on different banks
 constexpr int kRowB = kG + 4;    // padded LDS column of the staged B (floats)
-constexpr double kChainAbove = 0x1p+64;
+constexpr int kLive = -512;                  // exponent from which the chain registers hold A itself
+constexpr double kChainAbove = 0x1p+64 * 0x1p-512;   // 2^64 for the chain below kLive (scaled by 2^kLive)
 static_assert(kLT == kMultiPad, "tiles must fit the padding of the partial buffer");
 
 __device__ inline double ldexp_d(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
@@ -217,11 +218,17 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
 
         // ---- 2. l-tiles, software pipelined: the MFMAs of tile t read one A
         // buffer while the recurrence writes tile t+1 into the other ----------
-        double E = -1.0, O = 0.0;
-        // exponent turning the chain into A; a point exactly at a pole has
-        // s^m = 0 for m > 0 and contributes nothing (its chain is not bounded by
-        // a physical value there, so it must not reach A)
+        // The chain (E, O) of tables.hip times 2^q is A.  While q >= kLive the
+        // registers hold that product itself (live: A is read off them, and its
+        // values stay inside the FP32 range, so far inside FP64's); below, they
+        // hold the chain times 2^kLive, small enough that every A rounds to 0 in
+        // FP32 as it must (A < 2^(kLive + 192) there, the chain staying below
+        // 2^192 between checks), yet normal in FP64, so the chain loses nothing.
+        // Scaling by powers of two commutes with the rounding, so the A values
+        // are those of a chain kept apart from its exponent.  A point exactly at
+        // a pole has s^m = 0 for m > 0 and contributes nothing: it stays below.
         int q = (zr == 0.0 && zi == 0.0) ? -100000 : ze;
+        double E = -ldexp_d(1.0, q < kLive ? kLive : q), O = 0.0;
         // one recurrence pair (steps k, k+1 with coefficients c0, c1): its two A
         // values, split, into rows k/2 (even l) and 16 + k/2 (odd l) of buffer b
         auto recur_pair = [&](double c0, double c1, int k, int b) {
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
             E = fma(c0 * y, O, -E);
             O = fma(c1, E, -O);
             unsigned hi, lo;
-            split_pair(opaque((float)ldexp_d(E, q)), opaque((float)ldexp_d(O, q)), hi, lo);
+            split_pair(opaque((float)E), opaque((float)O), hi, lo);
             ah[(k >> 1) * kRowA] = (bf16_bits)hi;
             ah[(kLT / 2 + (k >> 1)) * kRowA] = (bf16_bits)(hi >> 16);
             al[(k >> 1) * kRowA] = (bf16_bits)lo;
@@ -287,13 +294,16 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
                 recur_pair(cf[2 * i], cf[2 * i + 1], 2 * i, b ^ 1);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            // keep the chain inside the FP64 range (growth < 2^255 per 64 steps)
-            {
+            // below kLive, keep the chain (registers x 2^-kLive) under 2^64 (its
+            // growth is < 2^255 per 64 steps), moving the excess into q, and go
+            // live once q reaches kLive
+            if (q < kLive) {
                 const double mx = fmax(fabs(E), fabs(O));
-                const int e = mx > kChainAbove ? frexp_exp_d(mx) : 0;
-                E = ldexp_d(E, -e);
-                O = ldexp_d(O, -e);
+                const int e = mx > kChainAbove ? frexp_exp_d(mx) - kLive : 0;
                 q += e;
+                const int sh = q < kLive ? -e : q - kLive - e;
+                E = ldexp_d(E, sh);
+                O = ldexp_d(O, sh);
             }
             // D[row][col]: row = 4*(lane/16) + r, col = lane % 16 (checked layout);
             // value v = 4 n + r.  Hand the values the partner adds to it.
@@ -317,7 +327,7 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
 }
 
 // out[v][column_start(m) + j] = sigma * sum_s partial[s][row(m) + j][2v, 2v+1]
-// (FP64 sum in slice order); one workgroup per order m
+// (compensated FP64 sum in slice order); one workgroup per order m
 __global__ void multi_finish_kernel(const float *__restrict__ partial, int n_slices, int nw,
                                     const double *__restrict__ sigma, int lmax, double *__restrict__ alm) {
     const int m = blockIdx.x;
@@ -327,14 +337,14 @@ __global__ void multi_finish_kernel(const float *__restrict__ partial, int n_sli
     const int nc = 2 * nw;
     for (int e = threadIdx.x; e < L * nw; e += blockDim.x) {
         const int v = e / L, j = e - v * L;
-        double re = 0.0, im = 0.0;
+        double re = 0.0, im = 0.0, cre = 0.0, cim = 0.0;
         for (int s = 0; s < n_slices; ++s) {
             const float2 p = *reinterpret_cast<const float2 *>(partial + ((int64_t)s * rows + r0 + j) * nc + 2 * v);
-            re += (double)p.x;
-            im += (double)p.y;
+            neumaier_add(re, cre, (double)p.x);
+            neumaier_add(im, cim, (double)p.y);
         }
         const double sg = sigma[c0 + j];
-        reinterpret_cast<double2 *>(alm)[(int64_t)v * T + c0 + j] = make_double2(sg * re, sg * im);
+        reinterpret_cast<double2 *>(alm)[(int64_t)v * T + c0 + j] = make_double2(sg * (re + cre), sg * (im + cim));
     }
 }
 

@@ -13,6 +13,14 @@ namespace ptalm {
 // entries so that an l-block may run past lmax without reading out of bounds.
 constexpr int kCoefPad = 64;
 
+// Neumaier's compensated addition: sum + c carries the exact running total to
+// within one rounding of the final result, whatever the order of magnitudes.
+__device__ inline void neumaier_add(double &sum, double &c, double v) {
+    const double t = sum + v;
+    c += (fabs(sum) >= fabs(v)) ? (sum - t) + v : (v - t) + sum;
+    sum = t;
+}
+
 __host__ __device__ inline int64_t tri_size(int lmax) { return (int64_t)(lmax + 1) * (lmax + 2) / 2; }
 
 // healpy index of (l, m)
