@@ -27,9 +27,12 @@
 //      recurrence of the next tile.  The two wavefronts that hold the same D
 //      block for the two point halves exchange half of it through LDS; each adds
 //      its half of the block for all 512 points into the slice's FP32 partial
-//      (read-modify-write, the first group of a slice stores).
-// The partial buffer pads every order by 32 rows, so whole tiles are read and
-// written without bounds tests.  A final pass sums the slices in FP64 in fixed
+//      (the first group of a slice stores; later groups add with the hardware
+//      FP32 atomic, which saves the load of the old value: one lane owns each
+//      value, so its adds reach the partial in program order and the result is
+//      that of a read-modify-write in group order).
+// The partial buffer pads every order by 32 rows, so whole tiles are written
+// without bounds tests.  A final pass sums the slices in FP64 in fixed
 // order and applies the output scale sigma_lm.  Every order is fixed, so
 // results are reproducible.
 #include "ptalm_internal.h"
@@ -252,13 +255,6 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
             const int jb = t * kLT;
             const int b = t & 1;
             float *pt = part + (int64_t)jb * NC;
-            // previous partials of the values this lane adds, fetched before the
-            // work that hides their latency
-            float prev[NOWN];
-#pragma unroll
-            for (int o = 0; o < NOWN; ++o) {
-                prev[o] = pt[own_offset(o)];
-            }
             // step coefficients of the next tile (the tile after the last reads
             // the table's padding; steps past lmax-m land in padding rows)
             double cf[kLT];
@@ -320,7 +316,11 @@ __global__ __launch_bounds__(kG) __attribute__((amdgpu_waves_per_eu(2))) void al
 #pragma unroll
             for (int o = 0; o < NOWN; ++o) {
                 const float mine = half ? dv[NOWN + o] : dv[o];
-                pt[own_offset(o)] = (first ? 0.f : prev[o]) + (mine + xr[o * 64]);
+                const float val = mine + xr[o * 64];
+                if (first)
+                    pt[own_offset(o)] = 0.f + val;
+                else
+                    (void)unsafeAtomicAdd(pt + own_offset(o), val);
             }
         }
     }
