@@ -475,7 +475,7 @@ __global__ void node_tables_kernel(int lmax, double *coef, double *sig) {
 // with the sums of the node weights against y_l).  Work decomposition of the
 // direct kernels: groups of 64*KP nodes, S node slices, R order ranges, one
 // wavefront per (slice, range); s^m as a mantissa with a binary exponent
-// advanced by s per order; the chain rescaled every 64 l; the four sums per l
+// advanced by s per order; the chain rescaled every 128 l; the four sums per l
 // reduced across lanes in a fixed order into the slice's partial column.
 // Per (node, l, m): 8 FP64 operations (chain 2, V - l F 2, P 2, Q 2).
 template <int KP, int LB>

@@ -29,13 +29,16 @@ __device__ inline void renorm(double &re, double &im, int &exponent) {
     exponent += e;
 }
 
-// Chain range control.  Over 64 steps the chain grows by less than 2^255 even
-// next to the poles at m ~ 3000; over 16 steps by less than 2^98 for any
-// m <= 16383.  FP64 chains are checked every 64 l against 2^64, FP32 chains
-// every 16 l against 2^16, so neither can overflow between checks.
+// Chain range control.  The chain grows fastest right after its start next to
+// a pole, where the step ratio is about x sqrt(2m / (l - m)): over 16 steps by
+// less than 2^98 for any m <= 16383, over 128 steps by less than 2^446 for
+// m ~ 3000 and 2^600 for any m <= 16383 (the normalised recurrence run on the
+// host at x up to 1 - 1e-12).  FP64 chains are checked every 128 l against
+// 2^64 (so they stay below 2^664), FP32 chains every 16 l against 2^16, so
+// neither can overflow between checks.
 template <typename RecT> struct ChainRange;
 template <> struct ChainRange<double> {
-    static constexpr int every_l = 64;
+    static constexpr int every_l = 128;
     static constexpr double above = 0x1p+64;
 };
 template <> struct ChainRange<float> {
