@@ -100,6 +100,9 @@ WORKLOADS = {
 }
 
 
+LONG_STEP_S = 20.0   # steps at least this long report their end as they finish
+
+
 class Budget:
     """Wall-clock budget of one bench run, counted from process start.  --steps and --warmup are
     upper limits: a step whose measured duration no longer fits is not started."""
@@ -161,6 +164,8 @@ def run_steps(step, sync, warmup, steps, budget, reserve_s=0.0, after_first=None
         for _ in range(more_w):
             print(f"[bench] warmup {label} {done_w}", file=sys.stderr, flush=True)
             step()
+            if step_s >= LONG_STEP_S:
+                sync()
             done_w += 1
         sync()
         t0 = time.perf_counter()
@@ -169,6 +174,11 @@ def run_steps(step, sync, warmup, steps, budget, reserve_s=0.0, after_first=None
               f"budget)", file=sys.stderr, flush=True)
     for i in range(n):
         step()
+        if step_s >= LONG_STEP_S:
+            # a long step ends with a synchronization and a progress line (one wait per
+            # step of tens of seconds costs nothing measurable; short steps stay queued)
+            sync()
+            print(f"[bench] timed {label} {timed + i + 1} of {timed + n} done", file=sys.stderr, flush=True)
     sync()
     elapsed = time.perf_counter() - t0
     timed += n

@@ -94,6 +94,26 @@ def test_timed_steps_come_before_extra_warmups():
     assert res["warmup_done"] == 1 and res["steps"] >= 3
 
 
+def test_long_steps_report_each_end(monkeypatch, capsys):
+    """Steps of tens of seconds end with a synchronization and a progress line each, so a run
+    of several such steps is never silent for more than one step; short steps stay queued
+    with a single synchronization after the timed loop."""
+    monkeypatch.setattr(bench, "LONG_STEP_S", 0.05)
+    log, syncs = [], []
+    budget = bench.Budget(0.0)
+    budget.end = time.monotonic() + 60.0
+    res = bench.run_steps(_fake_step(0.06, log), lambda: syncs.append(len(log)), 2, 4, budget)
+    err = capsys.readouterr().err
+    assert res["steps"] == 4 and res["warmup_done"] == 2
+    assert [f"timed step {k} of 4 done" in err for k in (1, 2, 3, 4)] == [True] * 4
+    assert all(n in syncs for n in range(2, 7))      # a synchronization after every step but the first
+    monkeypatch.setattr(bench, "LONG_STEP_S", 1e9)
+    log, syncs = [], []
+    res = bench.run_steps(_fake_step(0.01, log), lambda: syncs.append(len(log)), 1, 5, budget)
+    assert "done" not in capsys.readouterr().err.replace("0 done", "")
+    assert res["steps"] == 5 and syncs.count(6) == 1   # one synchronization after the timed loop
+
+
 def test_optional_run_is_kept_free_only_beside_two_timed_steps():
     log = []
     budget = bench.Budget(0.0)
