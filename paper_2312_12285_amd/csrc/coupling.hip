@@ -535,14 +535,16 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(double *__restrict__ Ag,
 constexpr int kSolveThreads = 256;
 constexpr int kLuPB = 16;   // row block of the triangular solves
 constexpr int kSolveLds = 20224;   // doubles of LDS per workgroup (factors and/or right-hand sides)
+constexpr int kSolveBatch = 16;    // global loads in flight per thread when filling LDS
 
 // Columns of the right-hand sides per workgroup of lu_solve_kernel, and whether
 // the factors are copied into LDS next to them (when both fit).
 inline void solve_shape(int nb, int *cols, bool *lu_in_lds) {
     const int room = kSolveLds - nb * nb;
     *lu_in_lds = room >= 16 * nb;
-    const int fit = *lu_in_lds ? room / nb : kSolveLds / nb;
-    *cols = fit >= 64 ? 64 : (fit >= 32 ? 32 : 16);
+    // 16 columns (the least that fits any nb <= 1024): more workgroups, and each
+    // thread's share of the rows (nb / 16) is shorter on the solve's critical path
+    *cols = 16;
 }
 
 // X = U^-1 L^-1 P [C^_b | R] for the columns [col0, col0 + cols) of that
@@ -553,16 +555,28 @@ template <bool kLuInLds>
 __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(const double *__restrict__ LUg,
                                                                  const int *__restrict__ perm, int nb,
                                                                  const double *__restrict__ R,
-                                                                 const double *__restrict__ cl_hat, int lmin,
-                                                                 int delta_l, int n1, int cols,
-                                                                 double *__restrict__ cb,
+                                                                 const double *__restrict__ chat_b, int n1,
+                                                                 int cols, double *__restrict__ cb,
                                                                  double *__restrict__ window) {
     __shared__ double lds[kSolveLds];
     const int tid = threadIdx.x;
     const double *LU = LUg;
     double *X = lds;   // nb x cols
+    // global loads in batches of kSolveBatch per thread, all issued before their stores
     if (kLuInLds) {
-        for (int e = tid; e < nb * nb; e += kSolveThreads) lds[e] = LUg[e];
+        for (int e0 = 0; e0 < nb * nb; e0 += kSolveThreads * kSolveBatch) {
+            double v[kSolveBatch];
+#pragma unroll
+            for (int u = 0; u < kSolveBatch; ++u) {
+                const int e = e0 + u * kSolveThreads + tid;
+                v[u] = e < nb * nb ? LUg[e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSolveBatch; ++u) {
+                const int e = e0 + u * kSolveThreads + tid;
+                if (e < nb * nb) lds[e] = v[u];
+            }
+        }
         LU = lds;
         X = lds + nb * nb;
     }
@@ -570,20 +584,22 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(const double *_
     const int c = tid % cols, r0 = tid / cols, rstep = kSolveThreads / cols;
     const int gc = col0 + c;
     const bool live = gc <= n1;
-    for (int i = r0; i < nb; i += rstep) {
-        double v = 0.0;
-        if (live) {
-            const int src = perm[i];
-            if (gc == 0) {
-                const int l0 = lmin + src * delta_l;
-                double s = 0.0;
-                for (int k = 0; k < delta_l; ++k) s += cl_hat[l0 + k];
-                v = s / delta_l;
-            } else {
-                v = R[(int64_t)src * n1 + gc - 1];
-            }
+    for (int i0 = r0; i0 < nb; i0 += rstep * kSolveBatch) {
+        int src[kSolveBatch];
+        double v[kSolveBatch];
+#pragma unroll
+        for (int u = 0; u < kSolveBatch; ++u) {
+            const int i = i0 + u * rstep;
+            src[u] = (live && i < nb) ? perm[i] : -1;
         }
-        X[i * cols + c] = v;
+#pragma unroll
+        for (int u = 0; u < kSolveBatch; ++u)
+            v[u] = src[u] < 0 ? 0.0 : (gc == 0 ? chat_b[src[u]] : R[(int64_t)src[u] * n1 + gc - 1]);
+#pragma unroll
+        for (int u = 0; u < kSolveBatch; ++u) {
+            const int i = i0 + u * rstep;
+            if (i < nb) X[i * cols + c] = v[u];
+        }
     }
     __syncthreads();
     // L y = P b and then U x = y, by row blocks of kLuPB: a block's own rows are
@@ -608,10 +624,18 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(const double *_
                 if (rb + a < re) X[(rb + a) * cols + c] = xb[a];
         }
         __syncthreads();
-        for (int i = re + r0; i < nb; i += rstep) {
-            double t = X[i * cols + c];
-            for (int j = rb; j < re; ++j) t = fma(-LU[i * nb + j], X[j * cols + c], t);
-            X[i * cols + c] = t;
+        {
+            double xj[kLuPB];   // the block's solved rows of this column
+#pragma unroll
+            for (int a = 0; a < kLuPB; ++a) xj[a] = rb + a < re ? X[(rb + a) * cols + c] : 0.0;
+#pragma unroll 4
+            for (int i = re + r0; i < nb; i += rstep) {
+                double t = X[i * cols + c];
+#pragma unroll
+                for (int a = 0; a < kLuPB; ++a)
+                    if (rb + a < re) t = fma(-LU[i * nb + rb + a], xj[a], t);
+                X[i * cols + c] = t;
+            }
         }
         __syncthreads();
     }
@@ -634,10 +658,18 @@ __global__ __launch_bounds__(kSolveThreads) void lu_solve_kernel(const double *_
                 if (re - 1 - a >= rb) X[(re - 1 - a) * cols + c] = xb[a];
         }
         __syncthreads();
-        for (int i = r0; i < rb; i += rstep) {
-            double t = X[i * cols + c];
-            for (int j = re - 1; j >= rb; --j) t = fma(-LU[i * nb + j], X[j * cols + c], t);
-            X[i * cols + c] = t;
+        {
+            double xj[kLuPB];   // xj[a] holds the solved row re - 1 - a of this column
+#pragma unroll
+            for (int a = 0; a < kLuPB; ++a) xj[a] = re - 1 - a >= rb ? X[(re - 1 - a) * cols + c] : 0.0;
+#pragma unroll 4
+            for (int i = r0; i < rb; i += rstep) {
+                double t = X[i * cols + c];
+#pragma unroll
+                for (int a = 0; a < kLuPB; ++a)
+                    if (re - 1 - a >= rb) t = fma(-LU[i * nb + re - 1 - a], xj[a], t);
+                X[i * cols + c] = t;
+            }
         }
         __syncthreads();
     }
@@ -835,8 +867,8 @@ hipError_t launch_coupling(const double *Wl, int lmax_w, const double *shot, dou
 
 size_t bandpower_scratch_doubles(int lmax, int nb) {
     const size_t n1 = (size_t)lmax + 1;
-    // R = theta M, Mbb and its factors, the row permutation (ints), N
-    return (size_t)nb * n1 + (size_t)nb * nb + ((size_t)nb + 1) / 2 + 1;
+    // R = theta M, Mbb and its factors, theta C^, the row permutation (ints), N
+    return (size_t)nb * n1 + (size_t)nb * nb + (size_t)nb + ((size_t)nb + 1) / 2 + 1;
 }
 
 hipError_t launch_bandpowers(const double *cl_hat, const double *M, const double *Wl, int lmax_w, int lmax, int lmin,
@@ -855,9 +887,14 @@ hipError_t launch_bandpowers(const double *cl_hat, const double *M, const double
     }
     double *R = scratch;
     double *Mbb = R + (size_t)nb * n1;
-    int *perm = (int *)(Mbb + (size_t)nb * nb);
+    double *chat_b = Mbb + (size_t)nb * nb;
+    int *perm = (int *)(chat_b + nb);
     hipLaunchKernelGGL(bin_rows_kernel, dim3(blocks_for((int64_t)nb * n1, 256)), dim3(256), 0, stream, M, n1, lmin,
                        delta_l, nb, (const double *)nullptr, R);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // (theta C^)_b, the first right-hand side
+    hipLaunchKernelGGL(bin_rows_kernel, dim3(blocks_for(nb, 256)), dim3(256), 0, stream, cl_hat, 1, lmin, delta_l, nb,
+                       (const double *)nullptr, chat_b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(binned_coupling_kernel, dim3(blocks_for((int64_t)nb * nb, 256)), dim3(256), 0, stream, R, n1,
                        lmin, delta_l, nb, Mbb);
@@ -872,11 +909,11 @@ hipError_t launch_bandpowers(const double *cl_hat, const double *M, const double
     solve_shape(nb, &cols, &lu_lds);
     const unsigned grid = (unsigned)((n1 + 1 + cols - 1) / cols);
     if (lu_lds)
-        hipLaunchKernelGGL(lu_solve_kernel<true>, dim3(grid), dim3(kSolveThreads), 0, stream, Mbb, perm, nb, R, cl_hat,
-                           lmin, delta_l, n1, cols, cb, window);
+        hipLaunchKernelGGL(lu_solve_kernel<true>, dim3(grid), dim3(kSolveThreads), 0, stream, Mbb, perm, nb, R,
+                           (const double *)chat_b, n1, cols, cb, window);
     else
-        hipLaunchKernelGGL(lu_solve_kernel<false>, dim3(grid), dim3(kSolveThreads), 0, stream, Mbb, perm, nb, R, cl_hat,
-                           lmin, delta_l, n1, cols, cb, window);
+        hipLaunchKernelGGL(lu_solve_kernel<false>, dim3(grid), dim3(kSolveThreads), 0, stream, Mbb, perm, nb, R,
+                           (const double *)chat_b, n1, cols, cb, window);
     return hipGetLastError();
 }
 
