@@ -510,23 +510,27 @@ __global__ __launch_bounds__(64) void spin_single_kernel(SpinArgs args) {
         spin_single_body<KP, LB, 1>(args, r, s, red);
 }
 
-// E = -sigma (S+ + S-) / 2, B = i sigma (S+ - S-) / 2 with S+-, the slice sums in
+// E = -sigma (S+ + S-) / 2, B = i sigma (S+ - S-) / 2 with S+-, the compensated slice sums in
 // slice order; entries with sigma = 0 (l < 2) are written as 0 without reading
 // the partials (never written for them).
 __global__ void spin_finish_kernel(const double *__restrict__ partial, int n_slices, const double *__restrict__ sigma,
                                    int64_t T, double *__restrict__ alm_e, double *__restrict__ alm_b) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < T; k += (int64_t)gridDim.x * blockDim.x) {
         const double sg = sigma[k];
-        double pr = 0.0, pi = 0.0, mr = 0.0, mi = 0.0;
+        double pr = 0.0, pi = 0.0, mr = 0.0, mi = 0.0, cpr = 0.0, cpi = 0.0, cmr = 0.0, cmi = 0.0;
         if (sg != 0.0) {
             for (int s = 0; s < n_slices; ++s) {
                 const double4 v = reinterpret_cast<const double4 *>(partial + (int64_t)s * 4 * T)[k];
-                pr += v.x;
-                pi += v.y;
-                mr += v.z;
-                mi += v.w;
+                neumaier_add(pr, cpr, v.x);
+                neumaier_add(pi, cpi, v.y);
+                neumaier_add(mr, cmr, v.z);
+                neumaier_add(mi, cmi, v.w);
             }
         }
+        pr += cpr;
+        pi += cpi;
+        mr += cmr;
+        mi += cmi;
         const double h = 0.5 * sg;
         reinterpret_cast<double2 *>(alm_e)[k] = make_double2(-h * (pr + mr), -h * (pi + mi));
         reinterpret_cast<double2 *>(alm_b)[k] = make_double2(-h * (pi - mi), h * (pr - mr));

@@ -650,7 +650,7 @@ __global__ __launch_bounds__(64) void node_sum_wave_kernel(NodeSumArgs a) {
     }
 }
 
-// a_lm = sig_l P_l + d_l sig_{l-1} Q_l with the slice sums in slice order; one
+// a_lm = sig_l P_l + d_l sig_{l-1} Q_l with the compensated slice sums in slice order; one
 // workgroup per order m.
 __global__ void node_finish_kernel(const double *__restrict__ partial, int n_slices, const double *__restrict__ sig,
                                    int lmax, double *__restrict__ alm) {
@@ -659,14 +659,18 @@ __global__ void node_finish_kernel(const double *__restrict__ partial, int n_sli
     const int64_t col = column_start(lmax, m);
     for (int l = m + threadIdx.x; l <= lmax; l += blockDim.x) {
         const int64_t k = col + (l - m);
-        double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0;
+        double pr = 0.0, pi = 0.0, qr = 0.0, qi = 0.0, cpr = 0.0, cpi = 0.0, cqr = 0.0, cqi = 0.0;
         for (int s = 0; s < n_slices; ++s) {
             const double4 v = reinterpret_cast<const double4 *>(partial + (int64_t)s * 4 * T)[k];
-            pr += v.x;
-            pi += v.y;
-            qr += v.z;
-            qi += v.w;
+            neumaier_add(pr, cpr, v.x);
+            neumaier_add(pi, cpi, v.y);
+            neumaier_add(qr, cqr, v.z);
+            neumaier_add(qi, cqi, v.w);
         }
+        pr += cpr;
+        pi += cpi;
+        qr += cqr;
+        qi += cqi;
         double re = sig[k] * pr, im = sig[k] * pi;
         if (l > m) {
             const double ll = l, mm = m;
