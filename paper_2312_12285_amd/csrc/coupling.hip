@@ -462,11 +462,28 @@ __global__ void binned_coupling_kernel(const double *__restrict__ R, int n1, int
 constexpr int kLuThreads = 1024;
 constexpr int kLuLdsMaxNb = 140;   // nb^2 doubles in LDS up to this size
 
+// One step of the pivot choice: combine with the lane rot places further round
+// the lane's row of 16 (DPP row rotation), keeping the larger |value| and on a
+// tie the lower row.
+template <int ROT>
+__device__ inline void lu_pivot_rotate(double &best, int &bi) {
+    constexpr int ctrl = 0x120 + ROT;   // row_ror:ROT
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(best), ctrl, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(best), ctrl, 0xF, 0xF, false);
+    const int oi = __builtin_amdgcn_update_dpp(0, bi, ctrl, 0xF, 0xF, false);
+    const double ov = __hiloint2double(hi, lo);
+    if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+    }
+}
+
 // LU factorisation with partial pivoting (largest |pivot|, lowest row on ties)
 // of the nb x nb row-major matrix Ag, in place, in one workgroup: afterwards
 // the strict lower triangle holds L (unit diagonal), the upper triangle U, and
 // perm[i] is the original row now at row i.  The matrix is worked on in LDS
-// when it fits.  Each step: wave 0 finds the pivot, the rows are swapped, and
+// when it fits.  Each step: wave 0 finds the pivot (lane-local scan, then DPP
+// rotations in rows of 16 and the four row results), the rows are swapped, and
 // every row below scales its multiplier and updates itself (one row per 32
 // threads).
 template <bool kInLds>
@@ -491,14 +508,30 @@ __global__ __launch_bounds__(kLuThreads) void lu_kernel(double *__restrict__ Ag,
                     bi = i;
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(best, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ov > best || (ov == best && oi < bi)) {
-                    best = ov;
-                    bi = oi;
-                }
+            // largest |value|, lowest row on ties: a total order, so any combining
+            // order gives the same row.  Within each row of 16 lanes by DPP
+            // rotations (every lane ends with its row's choice), then over the four
+            // rows from lanes 0, 16, 32, 48.
+            lu_pivot_rotate<8>(best, bi);
+            lu_pivot_rotate<4>(best, bi);
+            lu_pivot_rotate<2>(best, bi);
+            lu_pivot_rotate<1>(best, bi);
+            double rv[4];
+            int ri[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                rv[r] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(best), 16 * r),
+                                         __builtin_amdgcn_readlane(__double2loint(best), 16 * r));
+                ri[r] = __builtin_amdgcn_readlane(bi, 16 * r);
             }
+            best = rv[0];
+            bi = ri[0];
+#pragma unroll
+            for (int r = 1; r < 4; ++r)
+                if (rv[r] > best || (rv[r] == best && ri[r] < bi)) {
+                    best = rv[r];
+                    bi = ri[r];
+                }
             if (lane == 0) {
                 const int pr = bi < nb ? bi : k;
                 piv = pr;
