@@ -86,6 +86,24 @@ def test_coupling_capture_and_table_cache(lib, oracle):
     assert (np.abs(M[nz] - ref[nz]) / ref[nz]).max() <= 1e-12
 
 
+def test_release_cache_frees_and_rebuilds_coupling_tables(lib):
+    """ptalm_release_cache frees the kept lmax-only coupling tables (and reports success);
+    the next call for that lmax builds them again and gives the same matrix bit for bit."""
+    import torch
+    lmax, lmax_w = 257, 514
+    W = np.exp(-np.arange(lmax_w + 1) / 40.0)
+    W[0] = 4 * math.pi * 0.5
+    Wd = dev(W)
+    first = lib.coupling_matrix(Wd, lmax)
+    torch.cuda.synchronize()
+    lib.release_cache()
+    again = lib.coupling_matrix(Wd, lmax)
+    torch.cuda.synchronize()
+    assert torch.equal(first, again)
+    lib.release_cache()                      # twice in a row: nothing left to free, still OK
+    lib.release_cache()
+
+
 def test_full_sky_identity(lib):
     W = np.zeros(600)
     W[0] = 4 * math.pi
