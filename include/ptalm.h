@@ -103,9 +103,12 @@ typedef struct ptalm_opts {
 /*
  * Extended transform: precision and multi-weight batches (several weight
  * vectors sharing one position set).  With workspace != NULL the call uses
- * that buffer for its scratch (device memory, 256-byte aligned, ws_bytes >=
- * ptalm_workspace_bytes(...)) and allocates nothing, which allows capture into
- * a HIP graph; with NULL it allocates stream-ordered scratch itself.
+ * that buffer for its scratch (device memory of the calling device from
+ * hipMalloc or hipMallocAsync, 256-byte aligned, ws_bytes >=
+ * ptalm_workspace_bytes(...); the split-bf16 form adds into it with device
+ * float atomics, which host-coherent memory need not support) and allocates
+ * nothing, which allows capture into a HIP graph; with NULL it allocates
+ * stream-ordered scratch itself.
  * PTALM_EINVAL as above, or opts fields out of range, or a workspace that is
  * too small or misaligned.
  * PTALM_ENOTSUP if the (precision, n_weights, tile) combination has no kernel.
